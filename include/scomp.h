@@ -1,0 +1,260 @@
+/*
+ * scomp.h - C ABI of the MI355X stencil-composition library.
+ *
+ * The library forms finite-difference stencils by composition and applies
+ * them matrix-free on structured 2D/3D grids on a gfx950 GPU, inside
+ * conjugate-gradient solves of a biharmonic boundary-value problem and of an
+ * implicit Cahn-Hilliard step.
+ *
+ * Paper: A. Mishra, D. Salac, M. G. Knepley, "On the order of accuracy for
+ * finite difference approximations of partial differential equations using
+ * stencil composition".
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns an sc_status; SC_OK (0) is success. Nothing is thrown
+ *   across the ABI. sc_last_error() gives a human-readable message for the
+ *   most recent failure on the calling thread.
+ * - Stencils are opaque, library-owned, immutable handles created by
+ *   sc_stencil_create / sc_compose_stencil / sc_stencil_lincomb and released
+ *   with sc_stencil_free. They live in host memory only.
+ * - Grids (sc_grid) describe caller-owned DEVICE memory. The library never
+ *   frees or reallocates it. Axis 0 (x) is unit stride.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream). Calls that
+ *   only launch work (sc_apply_composed) are asynchronous on that stream;
+ *   solver calls (sc_solve_biharmonic, sc_ch_step, sc_grid_diagnostics)
+ *   return after their work on that stream has completed, because they
+ *   test convergence on the host.
+ * - Weights are exact rationals: weight k is num[k] / (den * h^p) where p is
+ *   the stencil's power of h (its derivative order). They are converted to
+ *   the grid's floating type once, per call.
+ */
+#ifndef SCOMP_H
+#define SCOMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t without pulling in the HIP headers. */
+typedef struct ihipStream_t* sc_stream_t;
+
+typedef enum sc_status {
+  SC_OK = 0,
+  SC_EINVAL = 1,       /* bad argument: shapes, sizes, dtypes, aliasing, NULL */
+  SC_EOVERFLOW = 2,    /* exact rational arithmetic would overflow int64 */
+  SC_EDEVICE = 3,      /* a HIP runtime call failed */
+  SC_ENOMEM = 4,       /* device workspace could not be allocated */
+  SC_ENOTCONV = 5,     /* iteration limit reached; statistics are filled */
+  SC_EBREAKDOWN = 6,   /* CG breakdown: p.Ap <= 0 or not finite */
+  SC_EUNSUPPORTED = 7  /* valid request outside what the kernels implement */
+} sc_status;
+
+typedef enum sc_dtype { SC_F64 = 0, SC_F32 = 1 } sc_dtype;
+
+/* How values outside the grid's interior are obtained when a stencil reads
+ * them: SC_BC_PERIODIC wraps indices modulo n (true modulo, so stencils wider
+ * than the grid alias correctly); SC_BC_HALO reads the ring of width
+ * grid.halo stored around the interior (which must be >= the radius). */
+typedef enum sc_bc { SC_BC_PERIODIC = 0, SC_BC_HALO = 1 } sc_bc;
+
+/* Arithmetic of the Krylov solves: plain FP64 CG, or FP32 CG (FP32 vectors
+ * and applies, FP64 dot-product accumulators) inside FP64 iterative
+ * refinement on the true residual. */
+typedef enum sc_precision { SC_PREC_F64 = 0, SC_PREC_F32_IR = 1 } sc_precision;
+
+typedef struct sc_stencil sc_stencil;
+
+/*
+ * A structured grid in device memory.
+ *   dim      2 or 3.
+ *   halo     width of the ring stored around the interior on every active
+ *            axis (0 allowed).
+ *   n[3]     interior points along x, y, z; n[2] must be 1 when dim == 2.
+ *   pitch[2] elements between consecutive rows (y) and planes (z);
+ *            pitch[0] >= n[0] + 2 halo, pitch[1] >= pitch[0] (n[1] + 2 halo).
+ *            pitch[1] is ignored in 2D.
+ *   dtype    sc_dtype of the elements.
+ *   data     device pointer to the first stored element (the ring corner).
+ * Interior element (i, j, k), with -halo <= i < n[0] + halo etc., sits at
+ *   data[(i + halo) + (j + halo) pitch[0] + (k + halo) pitch[1]]   (3D)
+ *   data[(i + halo) + (j + halo) pitch[0]]                           (2D).
+ */
+typedef struct sc_grid {
+  int32_t dim;
+  int32_t halo;
+  int64_t n[3];
+  int64_t pitch[2];
+  int32_t dtype;
+  void* data;
+} sc_grid;
+
+/* ---------------------------------------------------------------------------
+ * Stencils (host-side exact algebra)
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Create a stencil from npts taps: offsets[3*t .. 3*t+2] is the integer
+ * lattice offset u_t (unused components must be 0 when dim < 3), and the
+ * weight of tap t is num[t] / (den * h^hpow) (Sec. 2.1: weights
+ * proportional to h^-p). Repeated offsets are summed, zero weights dropped,
+ * and the result is reduced to lowest terms with den > 0.
+ * Errors: SC_EINVAL (dim not in 1..3, npts < 1, den == 0, NULL pointers,
+ * |offset| > 64), SC_EOVERFLOW.
+ */
+sc_status sc_stencil_create(int32_t dim, int32_t npts, const int32_t* offsets,
+                            const int64_t* num, int64_t den, int32_t hpow,
+                            sc_stencil** out);
+
+/*
+ * Stencil composition C = B(A) (Sec. 2.2, eq. (C=B(A))): the inner stencil A
+ * is applied first and the outer stencil B to its result, so
+ * C[u_i + v_j] += a_i b_j, the denominators multiply and the powers of h
+ * (derivative orders) add. Composition of translation-invariant stencils is
+ * commutative (the lemma of Sec. 2.2.1). `a` and `b` are the inner and outer
+ * stencils; both must have the same dim.
+ * Errors: SC_EINVAL (NULL, dim mismatch), SC_EOVERFLOW.
+ */
+sc_status sc_compose_stencil(const sc_stencil* a, const sc_stencil* b, sc_stencil** out);
+
+/*
+ * Linear combination sum_k (cnum[k]/cden[k]) h^{chpow[k]} S_k (Sec. 2.1: the
+ * Taylor sequences form a vector space). All terms must have the same dim
+ * and the same S_k.hpow - chpow[k], which becomes the result's hpow. Used to
+ * form operators such as I + dt eps^2 L o L - dt S L as one stencil.
+ * Errors: SC_EINVAL, SC_EOVERFLOW.
+ */
+sc_status sc_stencil_lincomb(int32_t n, const sc_stencil* const* terms, const int64_t* cnum,
+                             const int64_t* cden, const int32_t* chpow, sc_stencil** out);
+
+/*
+ * Read back a stencil. *npts is always written; offsets (3 * npts int32) and
+ * num (npts int64) are written only if non-NULL and capacity >= npts. Taps
+ * are in canonical order (z, then y, then x offset ascending).
+ */
+sc_status sc_stencil_get(const sc_stencil* s, int32_t* dim, int32_t* npts, int32_t capacity,
+                         int32_t* offsets, int64_t* num, int64_t* den, int32_t* hpow);
+
+/* Chebyshev radius max_t max_d |u_t,d|. */
+int32_t sc_stencil_radius(const sc_stencil* s);
+
+void sc_stencil_free(sc_stencil* s);
+
+/* ---------------------------------------------------------------------------
+ * Matrix-free application
+ * ------------------------------------------------------------------------- */
+
+/*
+ * out = S in on the interior of `out`, with weights num/(den h^p) rounded
+ * once to the grids' dtype: out(i) = sum_t w_t in(i + u_t) (the definition of
+ * applying a stencil, Sec. 2.1; for a composed stencil the taps are those of
+ * eq. (C=B(A)), so one pass replaces the two sequential passes of the
+ * factors). `in` and `out` must share dim, n and dtype, and must not
+ * overlap in memory. In SC_BC_HALO mode in->halo >= radius(s). Only the
+ * interior of `out` is written; its ring is left untouched.
+ * Supported: dim 2 with radius <= 4, dim 3 with radius <= 2 (any pattern
+ * inside those boxes). Asynchronous on `stream`.
+ * Errors: SC_EINVAL, SC_EUNSUPPORTED, SC_EDEVICE.
+ */
+sc_status sc_apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_grid* out,
+                            sc_bc bc, sc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Krylov solves
+ * ------------------------------------------------------------------------- */
+
+typedef struct sc_solve_opts {
+  double tol;           /* target true relative residual ||b - A x||_2 / ||b||_2 (FP64) */
+  int64_t max_iter;     /* cap on CG iterations (inner iterations under SC_PREC_F32_IR) */
+  int32_t precision;    /* sc_precision */
+  double inner_tol;     /* SC_PREC_F32_IR: residual reduction asked of each FP32 solve */
+  int32_t check_every;  /* CG iterations launched between host convergence checks */
+} sc_solve_opts;
+
+typedef struct sc_solve_stats {
+  int64_t iterations;   /* CG iterations performed (FP32 inner iterations under IR) */
+  int32_t outer;        /* true-residual evaluations / refinement steps */
+  double rel_residual;  /* true ||b - A x||_2 / ||b||_2 at return, FP64 on the device */
+  double bnorm;         /* ||b||_2 */
+  double seconds;       /* wall time of the call */
+} sc_solve_stats;
+
+/* Fill opts with defaults: tol 1e-10, max_iter 10^7, SC_PREC_F64,
+ * inner_tol 1e-4, check_every 64. */
+void sc_solve_opts_default(sc_solve_opts* opts);
+
+/*
+ * Biharmonic boundary-value problem (Sec. 3.3): A u = f at the unknowns,
+ * where A is the composed operator `op` scaled by h^-p (for example the
+ * 5/7-point Laplacian composed with itself) and the values on the ring of
+ * width radius(op) around the unknowns are prescribed by `g`. Writing
+ * u = x + g with x zero on the ring, the solve is textbook CG from the
+ * initial guess in `u` on
+ *     A0 x = f - A g_ring,
+ * A0 being `op` with a zero ring (symmetric positive definite for the
+ * composed Laplacian), to ||b - A0 x|| <= tol ||b|| checked on the true
+ * residual.
+ *   f  FP64 grid, the forcing at the unknowns (ring ignored).
+ *   g  FP64 grid with halo >= radius(op) holding the ring values (interior
+ *      ignored), or NULL for a zero ring.
+ *   u  FP64 grid: initial guess at the unknowns on entry, solution on
+ *      return; its ring is not touched.
+ * All three share dim and n. Supported: dim 2 radius <= 4, dim 3 radius <= 2.
+ * Workspace is allocated from a per-device pool owned by the library.
+ * Errors: SC_EINVAL, SC_EUNSUPPORTED, SC_ENOMEM, SC_EDEVICE,
+ * SC_ENOTCONV (stats filled, u holds the last iterate),
+ * SC_EBREAKDOWN (operator not positive definite on the iterates).
+ */
+sc_status sc_solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, const sc_grid* g,
+                              const sc_solve_opts* opts, sc_grid* u, sc_solve_stats* stats,
+                              sc_stream_t stream);
+
+/* Cahn-Hilliard step parameters (normalised form u_t = Lap(u^3 - u - eps^2 Lap u)). */
+typedef struct sc_ch_params {
+  double h;    /* grid spacing (periodic unit domain: h = 1/n) */
+  double eps;  /* interface width */
+  double dt;   /* time step */
+  double S;    /* linear stabilisation constant */
+} sc_ch_params;
+
+/*
+ * One Cahn-Hilliard step with the linear fourth-order part implicit and the
+ * non-linear part explicit (Sec. 4.1, eq. (cahn) and the IMEX treatment
+ * stated there), with linear stabilisation S:
+ *   (I + dt eps^2 L o L - dt S L) u^{n+1} = u^n + dt L((u^n)^3 - (1+S) u^n),
+ * on a periodic grid. `lap` is the Laplacian stencil L (p = 2); the library
+ * composes L o L with sc_compose_stencil's algebra and forms the operator as
+ * one stencil. The solve starts from x0 = u^n, which keeps the mean of u
+ * unchanged in exact arithmetic.
+ *   u  FP64 grid (periodic; halo ignored), advanced in place.
+ * Errors: as sc_solve_biharmonic.
+ */
+sc_status sc_ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_solve_opts* opts,
+                     sc_grid* u, sc_solve_stats* stats, sc_stream_t stream);
+
+/*
+ * Diagnostics of a periodic FP64 grid: mass = h^d sum u and the discrete
+ * free energy E = h^d sum[(u^2-1)^2/4 + eps^2/2 sum_axes ((u_{i+e}-u_i)/h)^2]
+ * (Sec. 4.1, free energy with a double well and gradient term). Either
+ * output pointer may be NULL. Reductions are deterministic (fixed order).
+ */
+sc_status sc_grid_diagnostics(const sc_grid* u, double h, double eps, double* mass,
+                              double* energy, sc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Errors and version
+ * ------------------------------------------------------------------------- */
+
+const char* sc_status_str(sc_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char* sc_last_error(void);
+/* Library version string. */
+const char* sc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCOMP_H */

@@ -48,6 +48,8 @@ def lib() -> ctypes.CDLL:
         L.or_cg.argtypes = [ctypes.c_int, P, ctypes.c_int, ctypes.c_int, P, P, P, P,
                             ctypes.c_double, ctypes.c_int64, P, P]
         L.or_cg.restype = ctypes.c_int
+        L.or_threads.argtypes = []
+        L.or_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 

@@ -33,6 +33,7 @@
  *                  and a vanishing second normal derivative).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -182,3 +183,6 @@ done:
   free(r); free(p); free(q);
   return status;
 }
+
+/* Number of OpenMP threads the apply loop uses. */
+int or_threads(void) { return omp_get_max_threads(); }

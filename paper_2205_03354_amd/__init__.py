@@ -1,0 +1,26 @@
+"""MI355X (gfx950) stencil composition: exact composition of finite-difference
+stencils and their matrix-free application in HIP kernels, inside CG solves
+of a biharmonic boundary-value problem and of an implicit Cahn-Hilliard step.
+
+The public calls mirror the C ABI in ``include/scomp.h``:
+``compose_stencil``, ``apply_composed``, ``solve_biharmonic``, ``ch_step``.
+"""
+
+from ._native import (  # noqa: F401
+    SC_BC_HALO,
+    SC_BC_PERIODIC,
+    SC_PREC_F32_IR,
+    SC_PREC_F64,
+    ScError,
+    SolveStats,
+    Stencil,
+    apply_composed,
+    ch_step,
+    compose_stencil,
+    grid_diagnostics,
+    grid_of,
+    solve_biharmonic,
+    stencil_lincomb,
+    version,
+)
+from . import stencils  # noqa: F401

@@ -1,0 +1,280 @@
+"""ctypes binding of ``libscomp.so`` (the gfx950 stencil-composition library).
+
+Argument marshalling only: every computation happens in the library (exact
+stencil algebra on the host, everything else in HIP kernels on the GPU).
+PyTorch supplies device memory and the current HIP stream. If the library
+is not built, importing this module raises; there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscomp.so")
+
+SC_OK, SC_EINVAL, SC_EOVERFLOW, SC_EDEVICE, SC_ENOMEM, SC_ENOTCONV, SC_EBREAKDOWN, SC_EUNSUPPORTED = range(8)
+SC_F64, SC_F32 = 0, 1
+SC_BC_PERIODIC, SC_BC_HALO = 0, 1
+SC_PREC_F64, SC_PREC_F32_IR = 0, 1
+
+EXPORTED = (
+    "sc_stencil_create", "sc_compose_stencil", "sc_stencil_lincomb", "sc_stencil_get",
+    "sc_stencil_radius", "sc_stencil_free", "sc_apply_composed", "sc_solve_opts_default",
+    "sc_solve_biharmonic", "sc_ch_step", "sc_grid_diagnostics", "sc_status_str",
+    "sc_last_error", "sc_version",
+)
+
+
+class ScError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class SCGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("halo", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("pitch", ctypes.c_int64 * 2), ("dtype", ctypes.c_int32), ("data", ctypes.c_void_p)]
+
+
+class SCSolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int32)]
+
+
+class SCSolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("outer", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("bnorm", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class SCChParams(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("eps", ctypes.c_double), ("dt", ctypes.c_double), ("S", ctypes.c_double)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python paper_2205_03354_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    L.sc_stencil_create.argtypes = [I32, I32, P, P, I64, I32, PP]
+    L.sc_compose_stencil.argtypes = [P, P, PP]
+    L.sc_stencil_lincomb.argtypes = [I32, P, P, P, P, PP]
+    L.sc_stencil_get.argtypes = [P, P, P, I32, P, P, P, P]
+    L.sc_stencil_radius.argtypes = [P]
+    L.sc_stencil_radius.restype = I32
+    L.sc_stencil_free.argtypes = [P]
+    L.sc_stencil_free.restype = None
+    L.sc_apply_composed.argtypes = [P, D, ctypes.POINTER(SCGrid), ctypes.POINTER(SCGrid), ctypes.c_int, P]
+    L.sc_solve_opts_default.argtypes = [ctypes.POINTER(SCSolveOpts)]
+    L.sc_solve_opts_default.restype = None
+    L.sc_solve_biharmonic.argtypes = [P, D, ctypes.POINTER(SCGrid), ctypes.POINTER(SCGrid),
+                                      ctypes.POINTER(SCSolveOpts), ctypes.POINTER(SCGrid),
+                                      ctypes.POINTER(SCSolveStats), P]
+    L.sc_ch_step.argtypes = [P, ctypes.POINTER(SCChParams), ctypes.POINTER(SCSolveOpts),
+                             ctypes.POINTER(SCGrid), ctypes.POINTER(SCSolveStats), P]
+    L.sc_grid_diagnostics.argtypes = [ctypes.POINTER(SCGrid), D, D, P, P, P]
+    L.sc_status_str.argtypes = [ctypes.c_int]
+    L.sc_status_str.restype = ctypes.c_char_p
+    L.sc_last_error.argtypes = []
+    L.sc_last_error.restype = ctypes.c_char_p
+    L.sc_version.argtypes = []
+    L.sc_version.restype = ctypes.c_char_p
+    for name in ("sc_stencil_create", "sc_compose_stencil", "sc_stencil_lincomb", "sc_stencil_get",
+                 "sc_apply_composed", "sc_solve_biharmonic", "sc_ch_step", "sc_grid_diagnostics"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != SC_OK:
+        msg = lib.sc_last_error().decode()
+        raise ScError(status, f"{lib.sc_status_str(status).decode()}: {msg}")
+
+
+# ---------------------------------------------------------------- stencils
+
+class Stencil:
+    """Library-owned exact stencil: weight t is num[t] / (den h^hpow)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            lib.sc_stencil_free(h)
+            self._h = None
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    @classmethod
+    def create(cls, dim: int, offsets: Sequence[Sequence[int]], num: Sequence[int], den: int = 1,
+               hpow: int = 0) -> "Stencil":
+        n = len(num)
+        offs = (ctypes.c_int32 * (3 * n))()
+        for t, o in enumerate(offsets):
+            o = list(o) + [0] * (3 - len(o))
+            offs[3 * t:3 * t + 3] = o[:3]
+        nums = (ctypes.c_int64 * n)(*[int(v) for v in num])
+        out = ctypes.c_void_p()
+        _check(lib.sc_stencil_create(dim, n, offs, nums, int(den), int(hpow), ctypes.byref(out)))
+        return cls(out.value)
+
+    def get(self) -> Tuple[int, list, list, int, int]:
+        """(dim, offsets [(x,y,z)], num, den, hpow) in canonical order."""
+        dim, npts, den, hp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib.sc_stencil_get(self._h, ctypes.byref(dim), ctypes.byref(npts), 0, None, None,
+                                  ctypes.byref(den), ctypes.byref(hp)))
+        n = npts.value
+        offs = (ctypes.c_int32 * (3 * n))()
+        nums = (ctypes.c_int64 * n)()
+        _check(lib.sc_stencil_get(self._h, None, None, n, offs, nums, None, None))
+        return dim.value, [tuple(offs[3 * t:3 * t + 3]) for t in range(n)], list(nums), den.value, hp.value
+
+    @property
+    def radius(self) -> int:
+        return int(lib.sc_stencil_radius(self._h))
+
+
+def compose_stencil(a: Stencil, b: Stencil) -> Stencil:
+    """C = B(A): `a` is the inner stencil, `b` the outer one."""
+    out = ctypes.c_void_p()
+    _check(lib.sc_compose_stencil(a.handle, b.handle, ctypes.byref(out)))
+    return Stencil(out.value)
+
+
+def stencil_lincomb(terms: Sequence[Tuple[int, int, int, Stencil]]) -> Stencil:
+    """sum (cnum/cden) h^chpow S over terms (cnum, cden, chpow, S)."""
+    n = len(terms)
+    hs = (ctypes.c_void_p * n)(*[t[3].handle.value for t in terms])
+    cn = (ctypes.c_int64 * n)(*[int(t[0]) for t in terms])
+    cd = (ctypes.c_int64 * n)(*[int(t[1]) for t in terms])
+    cp = (ctypes.c_int32 * n)(*[int(t[2]) for t in terms])
+    out = ctypes.c_void_p()
+    _check(lib.sc_stencil_lincomb(n, hs, cn, cd, cp, ctypes.byref(out)))
+    return Stencil(out.value)
+
+
+# ------------------------------------------------------------------- grids
+
+def grid_of(t, halo: int = 0) -> SCGrid:
+    """Describe a CUDA tensor holding a grid *including* its ring of width
+    `halo` (x is the last axis, unit stride)."""
+    import torch
+
+    if not t.is_cuda:
+        raise ValueError("grid tensors must live on the GPU")
+    if t.dtype == torch.float64:
+        dt = SC_F64
+    elif t.dtype == torch.float32:
+        dt = SC_F32
+    else:
+        raise ValueError("grid dtype must be float64 or float32")
+    if t.dim() not in (2, 3) or t.stride(-1) != 1:
+        raise ValueError("grid tensors must be 2D/3D with unit stride along x")
+    g = SCGrid()
+    g.dim = t.dim()
+    g.halo = halo
+    shape = list(t.shape)[::-1]  # x first
+    for a in range(3):
+        g.n[a] = (shape[a] - 2 * halo) if a < t.dim() else 1
+    g.pitch[0] = t.stride(-2)
+    g.pitch[1] = t.stride(-3) if t.dim() == 3 else 0
+    g.dtype = dt
+    g.data = t.data_ptr()
+    return g
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def apply_composed(st: Stencil, x, y, bc: int = SC_BC_PERIODIC, h: float = 1.0, halo: int = 0,
+                   out_halo: Optional[int] = None, stream=None):
+    """y = S x on the interior (asynchronous on the current stream)."""
+    gi = grid_of(x, halo)
+    go = grid_of(y, halo if out_halo is None else out_halo)
+    _check(lib.sc_apply_composed(st.handle, float(h), ctypes.byref(gi), ctypes.byref(go), int(bc),
+                                 _stream(stream)))
+    return y
+
+
+@dataclass
+class SolveStats:
+    iterations: int
+    outer: int
+    rel_residual: float
+    bnorm: float
+    seconds: float
+    status: int
+
+
+def _opts(tol, max_iter, precision, inner_tol, check_every) -> SCSolveOpts:
+    o = SCSolveOpts()
+    lib.sc_solve_opts_default(ctypes.byref(o))
+    o.tol = tol
+    o.max_iter = int(max_iter)
+    o.precision = int(precision)
+    o.inner_tol = inner_tol
+    o.check_every = int(check_every)
+    return o
+
+
+def _stats(s: SCSolveStats, status: int) -> SolveStats:
+    return SolveStats(int(s.iterations), int(s.outer), float(s.rel_residual), float(s.bnorm), float(s.seconds), status)
+
+
+def solve_biharmonic(op: Stencil, h: float, f, u, g=None, g_halo: int = 0, tol: float = 1e-10,
+                     max_iter: int = 10**7, precision: int = SC_PREC_F64, inner_tol: float = 1e-4,
+                     check_every: int = 64, raise_on_error: bool = True, stream=None) -> SolveStats:
+    """A u = f at the unknowns with the ring prescribed by g (see scomp.h)."""
+    gf, gu = grid_of(f, 0), grid_of(u, 0)
+    gg = ctypes.byref(grid_of(g, g_halo)) if g is not None else None
+    o = _opts(tol, max_iter, precision, inner_tol, check_every)
+    st = SCSolveStats()
+    status = lib.sc_solve_biharmonic(op.handle, float(h), ctypes.byref(gf), gg, ctypes.byref(o), ctypes.byref(gu),
+                                     ctypes.byref(st), _stream(stream))
+    if raise_on_error:
+        _check(status)
+    return _stats(st, status)
+
+
+def ch_step(lap: Stencil, u, h: float, eps: float, dt: float, S: float, tol: float = 1e-10,
+            max_iter: int = 10**6, precision: int = SC_PREC_F64, inner_tol: float = 1e-4,
+            check_every: int = 32, raise_on_error: bool = True, stream=None) -> SolveStats:
+    """One linearly stabilised semi-implicit Cahn-Hilliard step, in place on u."""
+    gu = grid_of(u, 0)
+    prm = SCChParams(h, eps, dt, S)
+    o = _opts(tol, max_iter, precision, inner_tol, check_every)
+    st = SCSolveStats()
+    status = lib.sc_ch_step(lap.handle, ctypes.byref(prm), ctypes.byref(o), ctypes.byref(gu), ctypes.byref(st),
+                            _stream(stream))
+    if raise_on_error:
+        _check(status)
+    return _stats(st, status)
+
+
+def grid_diagnostics(u, h: float, eps: float, stream=None) -> Tuple[float, float]:
+    """(mass, free energy) of a periodic FP64 grid."""
+    gu = grid_of(u, 0)
+    m, e = ctypes.c_double(), ctypes.c_double()
+    _check(lib.sc_grid_diagnostics(ctypes.byref(gu), float(h), float(eps), ctypes.byref(m), ctypes.byref(e),
+                                   _stream(stream)))
+    return m.value, e.value
+
+
+def version() -> str:
+    return lib.sc_version().decode()

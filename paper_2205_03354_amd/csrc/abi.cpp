@@ -1,0 +1,143 @@
+// extern "C" entry points declared in include/scomp.h. They translate
+// arguments, catch every C++ exception and record the error message; the
+// work itself lives in stencil.cpp, solver.cpp and the kernels.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace sc {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+const char* last_error_message() { return g_err; }
+
+}  // namespace sc
+
+#define SC_GUARD(body)                         \
+  try {                                        \
+    body                                       \
+  } catch (const std::bad_alloc&) {            \
+    ::sc::set_error("host allocation failed"); \
+    return SC_ENOMEM;                          \
+  } catch (...) {                              \
+    ::sc::set_error("internal error");         \
+    return SC_EINVAL;                          \
+  }
+
+extern "C" {
+
+sc_status sc_stencil_create(int32_t dim, int32_t npts, const int32_t* offsets, const int64_t* num,
+                            int64_t den, int32_t hpow, sc_stencil** out) {
+  SC_GUARD(return sc::stencil_create(dim, npts, offsets, num, den, hpow, out);)
+}
+
+sc_status sc_compose_stencil(const sc_stencil* a, const sc_stencil* b, sc_stencil** out) {
+  SC_GUARD(return sc::compose(a, b, out);)
+}
+
+sc_status sc_stencil_lincomb(int32_t n, const sc_stencil* const* terms, const int64_t* cnum,
+                             const int64_t* cden, const int32_t* chpow, sc_stencil** out) {
+  SC_GUARD(return sc::lincomb(n, terms, cnum, cden, chpow, out);)
+}
+
+sc_status sc_stencil_get(const sc_stencil* s, int32_t* dim, int32_t* npts, int32_t capacity,
+                         int32_t* offsets, int64_t* num, int64_t* den, int32_t* hpow) {
+  if (!s) {
+    sc::set_error("NULL stencil");
+    return SC_EINVAL;
+  }
+  const int32_t np = (int32_t)s->off.size();
+  if (dim) *dim = s->dim;
+  if (npts) *npts = np;
+  if (den) *den = s->den;
+  if (hpow) *hpow = s->hpow;
+  if (capacity >= np) {
+    for (int32_t t = 0; t < np; ++t) {
+      if (offsets) {
+        offsets[3 * t] = s->off[t][0];
+        offsets[3 * t + 1] = s->off[t][1];
+        offsets[3 * t + 2] = s->off[t][2];
+      }
+      if (num) num[t] = s->num[t];
+    }
+  } else if (offsets || num) {
+    sc::set_error("capacity %d < %d taps", capacity, np);
+    return SC_EINVAL;
+  }
+  return SC_OK;
+}
+
+int32_t sc_stencil_radius(const sc_stencil* s) {
+  if (!s) return -1;
+  int32_t r = 0;
+  for (const auto& o : s->off)
+    for (int d = 0; d < 3; ++d) r = std::max<int32_t>(r, o[d] < 0 ? -o[d] : o[d]);
+  return r;
+}
+
+void sc_stencil_free(sc_stencil* s) { delete s; }
+
+sc_status sc_apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_grid* out, sc_bc bc,
+                            sc_stream_t stream) {
+  SC_GUARD(return sc::apply_composed(s, h, in, out, bc, reinterpret_cast<hipStream_t>(stream));)
+}
+
+void sc_solve_opts_default(sc_solve_opts* o) {
+  if (!o) return;
+  o->tol = 1e-10;
+  o->max_iter = 10000000;
+  o->precision = SC_PREC_F64;
+  o->inner_tol = 1e-4;
+  o->check_every = 64;
+}
+
+sc_status sc_solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, const sc_grid* g,
+                              const sc_solve_opts* opts, sc_grid* u, sc_solve_stats* stats,
+                              sc_stream_t stream) {
+  SC_GUARD(return sc::solve_biharmonic(op, h, f, g, opts, u, stats, reinterpret_cast<hipStream_t>(stream));)
+}
+
+sc_status sc_ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_solve_opts* opts, sc_grid* u,
+                     sc_solve_stats* stats, sc_stream_t stream) {
+  SC_GUARD(return sc::ch_step(lap, prm, opts, u, stats, reinterpret_cast<hipStream_t>(stream));)
+}
+
+sc_status sc_grid_diagnostics(const sc_grid* u, double h, double eps, double* mass, double* energy,
+                              sc_stream_t stream) {
+  SC_GUARD(return sc::grid_diagnostics(u, h, eps, mass, energy, reinterpret_cast<hipStream_t>(stream));)
+}
+
+const char* sc_status_str(sc_status s) {
+  switch (s) {
+    case SC_OK: return "ok";
+    case SC_EINVAL: return "invalid argument";
+    case SC_EOVERFLOW: return "rational overflow";
+    case SC_EDEVICE: return "device error";
+    case SC_ENOMEM: return "out of memory";
+    case SC_ENOTCONV: return "not converged";
+    case SC_EBREAKDOWN: return "CG breakdown";
+    case SC_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* sc_last_error(void) { return sc::last_error_message(); }
+
+const char* sc_version(void) { return "scomp 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,183 @@
+// Shared definitions of the gfx950 stencil-composition library: tap
+// patterns, kernel-side weight packs, device scalars of the Krylov solves
+// and the deterministic single-pass grid reduction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace sc {
+
+// ---------------------------------------------------------------------------
+// Tap patterns. A kernel is specialised for a pattern P and radius R; the
+// taps it evaluates are the offsets of the (2R+1)^d box admitted by the
+// pattern, enumerated z-major, then y, then x ascending. A composed stencil
+// is run by the smallest instantiated pattern that contains all its offsets;
+// missing taps get weight 0.
+//   CROSS    : on an axis, |d| <= R                 (5/7-point Laplacians,
+//                                                    the 9-point fourth-order cross)
+//   DIAMOND  : |dx|+|dy|+|dz| <= R                  (Laplacian o Laplacian:
+//                                                    13-point 2D, 25-point 3D)
+//   CROSSBOX : on an axis with |d| <= R, or at most two non-zero components
+//              each <= R/2                          (fourth-order cross composed
+//                                                    with itself: 33-point 2D)
+//   BOX      : the full box                          (any stencil of radius R)
+// ---------------------------------------------------------------------------
+enum Pattern : int { PAT_CROSS = 0, PAT_DIAMOND = 1, PAT_CROSSBOX = 2, PAT_BOX = 3 };
+
+__host__ __device__ constexpr int iabs(int v) { return v < 0 ? -v : v; }
+__host__ __device__ constexpr int imax(int a, int b) { return a > b ? a : b; }
+
+__host__ __device__ constexpr bool in_pattern(int pat, int R, int dx, int dy, int dz) {
+  const int ax = iabs(dx), ay = iabs(dy), az = iabs(dz);
+  const int nz = (ax > 0) + (ay > 0) + (az > 0);
+  const int mx = imax(ax, imax(ay, az));
+  if (mx > R) return false;
+  switch (pat) {
+    case PAT_CROSS: return nz <= 1;
+    case PAT_DIAMOND: return ax + ay + az <= R;
+    case PAT_CROSSBOX: return nz <= 1 || (nz <= 2 && mx <= R / 2);
+    default: return true;
+  }
+}
+
+// Index of tap (dx,dy,dz) in the enumeration of pattern (pat, R) in `dim`
+// dimensions, or -1 if the offset is not part of the pattern.
+__host__ __device__ constexpr int tap_index(int pat, int R, int dim, int dx, int dy, int dz) {
+  int idx = 0;
+  const int zr = dim == 3 ? R : 0;
+  for (int z = -zr; z <= zr; ++z)
+    for (int y = -R; y <= R; ++y)
+      for (int x = -R; x <= R; ++x) {
+        if (!in_pattern(pat, R, x, y, z)) continue;
+        if (x == dx && y == dy && z == dz) return idx;
+        ++idx;
+      }
+  return -1;
+}
+
+__host__ __device__ constexpr int num_taps(int pat, int R, int dim) {
+  int n = 0;
+  const int zr = dim == 3 ? R : 0;
+  for (int z = -zr; z <= zr; ++z)
+    for (int y = -R; y <= R; ++y)
+      for (int x = -R; x <= R; ++x) n += in_pattern(pat, R, x, y, z) ? 1 : 0;
+  return n;
+}
+
+// Operations that apply a stencil in one sweep (see sweep2d.hpp).
+enum SweepKind : int {
+  K_APPLY = 0,    // out = S in
+  K_CGDIR = 1,    // p = r + beta p_old ; q = S p ; <p, q>  -> alpha
+  K_RESID = 2,    // r = b - S x ; <r, r>                   -> rr_true (and a CG (re)start)
+  K_BVPRHS = 3,   // b = f - S g_ring ; <b, b>              -> bb, rr_stop
+  K_CHRHS = 4     // rhs = u + dt S(u^3 - (1+S0) u) ; <rhs, rhs> -> bb, rr_stop
+};
+
+// Weights of one pattern instance, passed by value as a kernel argument (so
+// they live in scalar registers / the kernel-argument segment, with no
+// device allocation).
+template <typename T, int N>
+struct Taps {
+  T w[N];
+};
+
+// Device scalars of one Krylov solve. One reduction kernel at a time uses
+// `ticket` (kernels of one solve are serialised on its stream); the last
+// block resets it to 0, so no host-side clearing is needed between launches.
+struct alignas(64) DevScalars {
+  double rr;        // <r, r> of the current recurrence residual
+  double pq;        // <p, A p>
+  double alpha;     // rr / pq
+  double beta;      // rr_new / rr (0 right after a (re)start)
+  double rr_stop;   // stop when rr <= rr_stop
+  double bb;        // <b, b>
+  double rr_true;   // <b - A x, b - A x> of the last residual sweep
+  double scale;     // refinement scale s = ||r||
+  long long iter;   // iterations performed
+  int done;         // 0 running, 1 recurrence converged, 2 breakdown
+  unsigned int ticket;
+  double pad[5];
+};
+
+// ---------------------------------------------------------------------------
+// Compile-time loop helper: f(std::integral_constant<int, I>) for I in [B, E).
+// ---------------------------------------------------------------------------
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(static_cast<F&&>(f));
+  }
+}
+
+__host__ __device__ constexpr int pmod_c(int a, int n) { return ((a % n) + n) % n; }
+
+// Blocks of a launch are dealt round-robin to the 8 XCDs of the MI355X
+// (block b runs on XCD b % 8). Remap so that each XCD receives one
+// contiguous range of logical tiles: neighbouring tiles, which share halo
+// rows/planes, then hit the same XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  constexpr int NX = 8;
+  const int q = nb / NX, r = nb % NX;
+  const int x = b % NX, i = b / NX;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// Sum over the block (deterministic tree order); the result is valid in
+// thread 0. NT must be a multiple of 64.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v) {
+  static_assert(NT % 64 == 0, "block must be whole waves");
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if constexpr (NT == 64) {
+    return v;
+  } else {
+    __shared__ double red[NT / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) t += red[w];
+    }
+    return t;
+  }
+}
+
+// Single-pass deterministic grid reduction. Every block contributes `v`
+// (its partial sum, any thread's value is summed over the block) under the
+// index `slot` (the logical tile, fixed by the data it covers, not by the
+// scheduling order). The last block to arrive sums all partials in index
+// order and calls fin(total) from thread 0. Returns nothing; finalisers
+// write their results into DevScalars.
+template <int NT, typename Fin>
+__device__ __forceinline__ void grid_reduce(double v, int slot, int nslots, double* partials,
+                                            unsigned int* ticket, Fin&& fin) {
+  __shared__ int is_last;
+  const double bs = block_sum<NT>(v);
+  if (threadIdx.x == 0) {
+    partials[slot] = bs;
+    const unsigned int prev =
+        __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == (unsigned int)nslots - 1u);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nslots; i += NT) s += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double total = block_sum<NT>(s);
+  if (threadIdx.x == 0) {
+    fin(total);
+    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+}  // namespace sc

@@ -1,0 +1,223 @@
+// Element-wise kernels of the Krylov solves (no stencil): the CG update
+// sweep, the refinement cast / update, grid copies and the Cahn-Hilliard
+// diagnostics. All reductions are deterministic (fixed per-thread order,
+// fixed block tree, partials summed in block order by the last block).
+#include "internal.hpp"
+
+namespace sc {
+
+namespace {
+
+constexpr int kNT = 256;
+
+// Rows [r0, r1) of the interior assigned to this block; row rho is
+// (j, k) = (rho % n1, rho / n1).
+struct RowRange {
+  int64_t r0, r1;
+};
+__device__ __forceinline__ RowRange block_rows(int64_t nrows) {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  return {b * nrows / nb, (b + 1) * nrows / nb};
+}
+__device__ __forceinline__ int64_t row_offset(int64_t rho, int64_t n1, int64_t pitch, int64_t zpitch) {
+  const int64_t k = rho / n1, j = rho - k * n1;
+  return k * zpitch + j * pitch;
+}
+
+// x += alpha p ; r -= alpha q ; rr_new = <r, r>  (then beta, convergence)
+template <typename T>
+__global__ void __launch_bounds__(kNT)
+    cg_update_kernel(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                     const T* __restrict__ q, int64_t pitch, int64_t zpitch, int64_t n0, int64_t n1,
+                     int64_t n2, DevScalars* s, double* partials) {
+  if (s->done) return;
+  const T alpha = (T)s->alpha;
+  const RowRange rr = block_rows(n1 * n2);
+  double dot = 0.0;
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t o = row_offset(rho, n1, pitch, zpitch);
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) {
+      const T pv = p[o + i], qv = q[o + i];
+      x[o + i] = x[o + i] + alpha * pv;
+      const T rv = r[o + i] - alpha * qv;
+      r[o + i] = rv;
+      dot += (double)rv * (double)rv;
+    }
+  }
+  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s->ticket, [&](double total) {
+    s->iter += 1;
+    if (total <= s->rr_stop) {
+      s->done = 1;
+    }
+    s->beta = total / s->rr;
+    s->rr = total;
+  });
+}
+
+__global__ void __launch_bounds__(kNT)
+    ir_prepare_kernel(const double* __restrict__ r64, int64_t p64, int64_t z64, float* __restrict__ r32,
+                      float* __restrict__ d32, int64_t p32, int64_t z32, int64_t n0, int64_t n1,
+                      int64_t n2, const DevScalars* s64, DevScalars* s32, double inner_tol2,
+                      double* partials) {
+  const double inv = 1.0 / sqrt(s64->rr_true);
+  const RowRange rr = block_rows(n1 * n2);
+  double dot = 0.0;
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t o64 = row_offset(rho, n1, p64, z64);
+    const int64_t o32 = row_offset(rho, n1, p32, z32);
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) {
+      const float v = (float)(r64[o64 + i] * inv);
+      r32[o32 + i] = v;
+      d32[o32 + i] = 0.0f;
+      dot += (double)v * (double)v;
+    }
+  }
+  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s32->ticket, [&](double total) {
+    s32->rr = total;
+    s32->rr_stop = inner_tol2 * total;
+    s32->beta = 0.0;
+    s32->done = total > 0.0 ? 0 : 1;
+  });
+}
+
+__global__ void __launch_bounds__(kNT)
+    ir_update_kernel(double* __restrict__ x64, int64_t p64, int64_t z64, const float* __restrict__ d32,
+                     int64_t p32, int64_t z32, int64_t n0, int64_t n1, int64_t n2,
+                     const DevScalars* s64) {
+  const double scale = sqrt(s64->rr_true);
+  const RowRange rr = block_rows(n1 * n2);
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t o64 = row_offset(rho, n1, p64, z64);
+    const int64_t o32 = row_offset(rho, n1, p32, z32);
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) x64[o64 + i] += scale * (double)d32[o32 + i];
+  }
+}
+
+__global__ void __launch_bounds__(kNT)
+    copy_kernel(const double* __restrict__ src, int64_t sp, int64_t sz, double* __restrict__ dst,
+                int64_t dp, int64_t dz, int64_t n0, int64_t n1, int64_t n2) {
+  const RowRange rr = block_rows(n1 * n2);
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t os = row_offset(rho, n1, sp, sz);
+    const int64_t od = row_offset(rho, n1, dp, dz);
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) dst[od + i] = src[os + i];
+  }
+}
+
+__global__ void __launch_bounds__(kNT)
+    diagnostics_kernel(const double* __restrict__ u, int64_t pitch, int64_t zpitch, int dim,
+                       int64_t n0, int64_t n1, int64_t n2, double* partials, unsigned int* ticket,
+                       double* out3) {
+  const RowRange rr = block_rows(n1 * n2);
+  double m = 0.0, bulk = 0.0, grad = 0.0;
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t k = rho / n1, j = rho - k * n1;
+    const int64_t o = k * zpitch + j * pitch;
+    const int64_t jn = (j + 1 == n1) ? 0 : j + 1;
+    const int64_t oy = k * zpitch + jn * pitch;
+    const int64_t kn = (k + 1 == n2) ? 0 : k + 1;
+    const int64_t oz = kn * zpitch + j * pitch;
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) {
+      const double v = u[o + i];
+      const int64_t in = (i + 1 == n0) ? 0 : i + 1;
+      const double dx = u[o + in] - v;
+      const double dy = u[oy + i] - v;
+      double g = dx * dx + dy * dy;
+      if (dim == 3) {
+        const double dz = u[oz + i] - v;
+        g += dz * dz;
+      }
+      const double w = v * v - 1.0;
+      m += v;
+      bulk += 0.25 * w * w;
+      grad += g;
+    }
+  }
+  __shared__ int is_last;
+  const double bm = block_sum<kNT>(m);
+  const double bb = block_sum<kNT>(bulk);
+  const double bg = block_sum<kNT>(grad);
+  const int nb = (int)gridDim.x;
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = bm;
+    partials[nb + blockIdx.x] = bb;
+    partials[2 * nb + blockIdx.x] = bg;
+    const unsigned int prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = prev == (unsigned int)nb - 1u;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  double t[3];
+  for (int c = 0; c < 3; ++c) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kNT)
+      s += __hip_atomic_load(partials + c * nb + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t[c] = block_sum<kNT>(s);
+  }
+  if (threadIdx.x == 0) {
+    out3[0] = t[0];
+    out3[1] = t[1];
+    out3[2] = t[2];
+    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+int elem_blocks(const int64_t* n) {
+  const int64_t rows = n[1] * n[2];
+  return (int)(rows < kElemBlocks ? rows : kElemBlocks);
+}
+
+}  // namespace
+
+hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
+                            const Layout& lay, const int64_t* n, DevScalars* s, double* partials,
+                            hipStream_t st) {
+  const int nb = elem_blocks(n);
+  if (dtype == SC_F64) {
+    hipLaunchKernelGGL(cg_update_kernel<double>, dim3(nb), dim3(kNT), 0, st, (double*)x, (double*)r,
+                       (const double*)p, (const double*)q, lay.pitch, lay.zpitch, n[0], n[1], n[2], s,
+                       partials);
+  } else {
+    hipLaunchKernelGGL(cg_update_kernel<float>, dim3(nb), dim3(kNT), 0, st, (float*)x, (float*)r,
+                       (const float*)p, (const float*)q, lay.pitch, lay.zpitch, n[0], n[1], n[2], s,
+                       partials);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_prepare(const double* r64, const Layout& l64, float* r32, float* d32,
+                             const Layout& l32, const int64_t* n, DevScalars* s64, DevScalars* s32,
+                             double inner_tol2, double* partials, hipStream_t st) {
+  const int nb = elem_blocks(n);
+  hipLaunchKernelGGL(ir_prepare_kernel, dim3(nb), dim3(kNT), 0, st, r64, l64.pitch, l64.zpitch, r32,
+                     d32, l32.pitch, l32.zpitch, n[0], n[1], n[2], s64, s32, inner_tol2, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_update(double* x64, const Layout& l64, const float* d32, const Layout& l32,
+                            const int64_t* n, const DevScalars* s64, hipStream_t st) {
+  const int nb = elem_blocks(n);
+  hipLaunchKernelGGL(ir_update_kernel, dim3(nb), dim3(kNT), 0, st, x64, l64.pitch, l64.zpitch, d32,
+                     l32.pitch, l32.zpitch, n[0], n[1], n[2], s64);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, int64_t sp, int64_t sz, double* dst, int64_t dp, int64_t dz,
+                       const int64_t* n, hipStream_t st) {
+  const int nb = elem_blocks(n);
+  hipLaunchKernelGGL(copy_kernel, dim3(nb), dim3(kNT), 0, st, src, sp, sz, dst, dp, dz, n[0], n[1],
+                     n[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(const double* u, int64_t pitch, int64_t zpitch, int dim,
+                              const int64_t* n, double* partials, unsigned int* ticket, double* out3,
+                              hipStream_t st) {
+  const int nb = elem_blocks(n);
+  hipLaunchKernelGGL(diagnostics_kernel, dim3(nb), dim3(kNT), 0, st, u, pitch, zpitch, dim, n[0], n[1],
+                     n[2], partials, ticket, out3);
+  return hipGetLastError();
+}
+
+}  // namespace sc

@@ -1,0 +1,152 @@
+// Host-side internals of the stencil-composition library: the stencil
+// object, kernel-pattern selection, launch descriptors and error handling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/scomp.h"
+#include "common.hpp"
+
+// Exact stencil: weight of tap t is num[t] / (den * h^hpow). Taps are in
+// canonical order (z, y, x ascending), without duplicates or zero weights,
+// and gcd(num..., den) == 1 with den > 0.
+struct sc_stencil {
+  int dim = 0;
+  int hpow = 0;
+  int64_t den = 1;
+  std::vector<std::array<int32_t, 3>> off;
+  std::vector<int64_t> num;
+};
+
+namespace sc {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+const char* last_error_message();
+
+#define SC_HIP_CHECK(expr)                                                        \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      ::sc::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                      __LINE__);                                                  \
+      return SC_EDEVICE;                                                          \
+    }                                                                             \
+  } while (0)
+
+// ------------------------------------------------------- kernel stencils
+constexpr int kMaxTaps = 128;
+
+// The stencil arranged for one kernel instance: pattern, radius and the
+// weights (already divided by den * h^p) in the pattern's tap order.
+struct KStencil {
+  int dim = 0;
+  int pat = 0;
+  int R = 0;
+  int ntaps = 0;
+  double w[kMaxTaps] = {};
+};
+
+// Choose the cheapest instantiated (pattern, radius) containing every tap of
+// the (already scaled) stencil given by offsets and weights.
+sc_status make_kstencil(int dim, const std::vector<std::array<int32_t, 3>>& off,
+                        const std::vector<long double>& w, KStencil* out);
+// Same, from an exact stencil and a grid spacing.
+sc_status make_kstencil(const sc_stencil* s, double h, KStencil* out);
+
+// ------------------------------------------------------------- launches
+struct SweepLaunch {
+  int kind = 0;        // SweepKind
+  int dtype = SC_F64;  // SC_F64 / SC_F32
+  bool periodic = true;
+  const KStencil* ks = nullptr;
+  const void* in = nullptr;
+  const void* in2 = nullptr;
+  const void* aux = nullptr;
+  void* out = nullptr;
+  void* out2 = nullptr;
+  int64_t pin = 0, pin2 = 0, paux = 0, pout = 0, pout2 = 0;
+  int64_t zin = 0, zin2 = 0, zaux = 0, zout = 0, zout2 = 0;
+  int64_t n[3] = {1, 1, 1};
+  DevScalars* scal = nullptr;
+  double* partials = nullptr;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  int flag = 0;
+  bool vec_store = false;
+};
+
+// Number of blocks (= partial-sum slots) the sweep will launch.
+int sweep_blocks(const SweepLaunch& L);
+// Launch; returns hipErrorInvalidValue (with sc_last_error set) for a
+// (kind, dtype, boundary, pattern, radius) combination with no kernel.
+hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st);
+
+// Instantiation parts (dispatch.hip compiled once per part).
+hipError_t part_apply2d_f64(const SweepLaunch& L, hipStream_t st);
+hipError_t part_apply2d_f32(const SweepLaunch& L, hipStream_t st);
+hipError_t part_solve2d_f64_periodic(const SweepLaunch& L, hipStream_t st);
+hipError_t part_solve2d_f64_ring(const SweepLaunch& L, hipStream_t st);
+hipError_t part_solve2d_f32(const SweepLaunch& L, hipStream_t st);
+hipError_t part_apply3d(const SweepLaunch& L, hipStream_t st);
+hipError_t part_solve3d_f64(const SweepLaunch& L, hipStream_t st);
+hipError_t part_solve3d_f32(const SweepLaunch& L, hipStream_t st);
+
+// Vector layout of solver workspace: pointers address the interior
+// (0,0,0) element, rows of `pitch` elements, planes of `zpitch`.
+struct Layout {
+  int64_t pitch = 0;
+  int64_t zpitch = 0;
+  int halo = 0;
+};
+
+constexpr int kElemBlocks = 1024;  // blocks of the element-wise kernels
+
+hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
+                            const Layout& lay, const int64_t* n, DevScalars* s, double* partials,
+                            hipStream_t st);
+// r32 = r64 / sqrt(s64->rr_true); d32 = 0; inner scalars (re)started with
+// rr_stop = inner_tol^2 <r32, r32>.
+hipError_t launch_ir_prepare(const double* r64, const Layout& l64, float* r32, float* d32,
+                             const Layout& l32, const int64_t* n, DevScalars* s64,
+                             DevScalars* s32, double inner_tol2, double* partials,
+                             hipStream_t st);
+// x64 += sqrt(s64->rr_true) * d32
+hipError_t launch_ir_update(double* x64, const Layout& l64, const float* d32, const Layout& l32,
+                            const int64_t* n, const DevScalars* s64, hipStream_t st);
+// Copy the interior of one FP64 grid view to another.
+hipError_t launch_copy(const double* src, int64_t sp, int64_t sz, double* dst, int64_t dp,
+                       int64_t dz, const int64_t* n, hipStream_t st);
+// mass = sum u, grad = sum_axes (u_{i+e} - u_i)^2, bulk = sum (u^2-1)^2/4,
+// periodic; results into out[3] (device) via a deterministic reduction.
+hipError_t launch_diagnostics(const double* u, int64_t pitch, int64_t zpitch, int dim,
+                              const int64_t* n, double* partials, unsigned int* ticket,
+                              double* out3, hipStream_t st);
+
+// ------------------------------------------------------ entry-point bodies
+sc_status stencil_create(int32_t dim, int32_t npts, const int32_t* offsets, const int64_t* num,
+                         int64_t den, int32_t hpow, sc_stencil** out);
+sc_status compose(const sc_stencil* a, const sc_stencil* b, sc_stencil** out);
+sc_status lincomb(int32_t n, const sc_stencil* const* terms, const int64_t* cnum, const int64_t* cden,
+                  const int32_t* chpow, sc_stencil** out);
+sc_status apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_grid* out, sc_bc bc,
+                         hipStream_t st);
+sc_status solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, const sc_grid* g,
+                           const sc_solve_opts* opts, sc_grid* u, sc_solve_stats* stats, hipStream_t st);
+sc_status ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_solve_opts* opts, sc_grid* u,
+                  sc_solve_stats* stats, hipStream_t st);
+sc_status grid_diagnostics(const sc_grid* u, double h, double eps, double* mass, double* energy,
+                           hipStream_t st);
+
+// --------------------------------------------------------- workspace pool
+// Grow-only per-device cache of device allocations (never returned to the
+// driver before process exit).
+void* pool_alloc(size_t bytes);
+void pool_free(void* p);
+
+}  // namespace sc

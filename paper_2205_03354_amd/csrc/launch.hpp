@@ -1,0 +1,117 @@
+// Launch helpers shared by the kernel-instantiation translation units.
+#pragma once
+
+#include <cstdlib>
+
+#include "internal.hpp"
+#include "sweep3d.hpp"
+
+namespace sc {
+
+// Output rows (2D) per tile: aim at >= ~2048 blocks (8 per CU) without
+// making tiles so short that the 2R halo rows dominate.
+inline int tile_rows_2d(int64_t n1, int64_t tiles_x, int R) {
+  if (const char* e = std::getenv("SCOMP_TY2D")) {
+    const int v = std::atoi(e);
+    if (v > 0) return v;
+  }
+  int64_t ty = (n1 * tiles_x + 2047) / 2048;
+  const int64_t lo = 8 * R > 16 ? 8 * R : 16;
+  if (ty < lo) ty = lo;
+  if (ty > n1) ty = n1;
+  if (ty < 1) ty = 1;
+  return (int)ty;
+}
+
+// Planes (3D) per tile.
+inline int tile_planes_3d(int64_t n2, int64_t xy_tiles, int R) {
+  if (const char* e = std::getenv("SCOMP_TZ3D")) {
+    const int v = std::atoi(e);
+    if (v > 0) return v;
+  }
+  int64_t tz = (n2 * xy_tiles + 1023) / 1024;
+  const int64_t lo = 4 * R > 8 ? 4 * R : 8;
+  if (tz < lo) tz = lo;
+  if (tz > n2) tz = n2;
+  if (tz < 1) tz = 1;
+  return (int)tz;
+}
+
+template <typename T>
+SweepArgs<T> make_args(const SweepLaunch& L) {
+  SweepArgs<T> a{};
+  a.in = static_cast<const T*>(L.in);
+  a.in2 = static_cast<const T*>(L.in2);
+  a.aux = static_cast<const T*>(L.aux);
+  a.out = static_cast<T*>(L.out);
+  a.out2 = static_cast<T*>(L.out2);
+  a.pin = L.pin; a.pin2 = L.pin2; a.paux = L.paux; a.pout = L.pout; a.pout2 = L.pout2;
+  a.zin = L.zin; a.zin2 = L.zin2; a.zaux = L.zaux; a.zout = L.zout; a.zout2 = L.zout2;
+  a.n0 = L.n[0]; a.n1 = L.n[1]; a.n2 = L.n[2];
+  a.scal = L.scal;
+  a.partials = L.partials;
+  a.c0 = L.c0; a.c1 = L.c1; a.c2 = L.c2;
+  a.flag = L.flag;
+  a.vec_store = L.vec_store ? 1 : 0;
+  return a;
+}
+
+template <typename T, int N>
+Taps<T, N> make_taps(const KStencil& ks) {
+  Taps<T, N> t{};
+  for (int i = 0; i < N; ++i) t.w[i] = (T)ks.w[i];
+  return t;
+}
+
+// Geometry of a 2D launch with NT threads per block.
+template <typename T, int NT>
+inline void geom2d(const SweepLaunch& L, int R, SweepArgs<T>& a, int* blocks) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  const int64_t TX = (int64_t)NT * VEC;
+  const int64_t tx = (L.n[0] + TX - 1) / TX;
+  a.ty = tile_rows_2d(L.n[1], tx, R);
+  const int64_t ty = (L.n[1] + a.ty - 1) / a.ty;
+  a.tiles_a = (int)tx;
+  a.tiles_b = (int)ty;
+  a.small = (L.n[0] < 2 * R + 8 || L.n[1] < 2 * R + 8) ? 1 : 0;
+  *blocks = (int)(tx * ty);
+}
+
+template <typename T, int NT>
+inline void geom3d(const SweepLaunch& L, int R, SweepArgs<T>& a, int* blocks) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int TX = 64;
+  constexpr int TY = (NT / (TX / VEC)) * 2;
+  const int64_t tx = (L.n[0] + TX - 1) / TX;
+  const int64_t ty = (L.n[1] + TY - 1) / TY;
+  a.tiles_x2 = (int)tx;
+  a.tiles_a = (int)(tx * ty);
+  a.ty = tile_planes_3d(L.n[2], tx * ty, R);
+  a.tiles_b = (int)((L.n[2] + a.ty - 1) / a.ty);
+  a.small = (L.n[0] < 2 * R + 8 || L.n[1] < 2 * R + 8 || L.n[2] < 2 * R + 8) ? 1 : 0;
+  *blocks = a.tiles_a * a.tiles_b;
+}
+
+template <typename T, int KIND, int PAT, int R, bool PER, int NT>
+hipError_t run2d(const SweepLaunch& L, hipStream_t st) {
+  SweepArgs<T> a = make_args<T>(L);
+  int blocks = 0;
+  geom2d<T, NT>(L, R, a, &blocks);
+  const auto taps = make_taps<T, num_taps(PAT, R, 2)>(*L.ks);
+  hipLaunchKernelGGL((sweep2d_kernel<T, KIND, PAT, R, PER, NT>), dim3(blocks), dim3(NT), 0, st, a,
+                     taps);
+  return hipGetLastError();
+}
+
+template <typename T, int KIND, int PAT, int R, bool PER, int NT>
+hipError_t run3d(const SweepLaunch& L, hipStream_t st) {
+  SweepArgs<T> a = make_args<T>(L);
+  int blocks = 0;
+  geom3d<T, NT>(L, R, a, &blocks);
+  const auto taps = make_taps<T, num_taps(PAT, R, 3)>(*L.ks);
+  hipLaunchKernelGGL((sweep3d_kernel<T, KIND, PAT, R, PER, NT>), dim3(blocks), dim3(NT), 0, st, a,
+                     taps);
+  return hipGetLastError();
+}
+
+}  // namespace sc

@@ -1,0 +1,151 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* the shared library loads and exports every function declared in
+  include/scomp.h;
+* the exact stencil algebra behind sc_compose_stencil / sc_stencil_lincomb
+  matches the oracle's independent rational composition bit-exactly;
+* argument validation and error reporting.
+"""
+
+import ctypes
+import os
+import re
+from fractions import Fraction as F
+
+import pytest
+
+from oracle import rational as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "scomp.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sc_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2205_03354_amd import _native
+
+    return _native
+
+
+def test_header_symbols_exported(native):
+    names = _declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(native.lib, name), name
+    assert set(native.EXPORTED) == set(names)
+
+
+def test_version_and_status_strings(native):
+    assert "gfx950" in native.version()
+    assert native.lib.sc_status_str(0) == b"ok"
+
+
+def _lib_stencil(native, st: R.RStencil):
+    nums, den = st.integer_form()
+    offs = sorted(nums)
+    return native.Stencil.create(st.dim, offs, [nums[o] for o in offs], den, st.p)
+
+
+def _as_rational(native, s) -> R.RStencil:
+    dim, offs, nums, den, hp = s.get()
+    return R.RStencil(dim, hp, {tuple(o[:dim]): F(v, den) for o, v in zip(offs, nums)})
+
+
+@pytest.mark.parametrize("name", ["lap2", "lap2_4th", "lap3", "fwd", "mixed"])
+def test_compose_matches_oracle(native, name):
+    # The factors are handed over exactly; the composition itself is computed
+    # independently by the library and by the oracle.
+    pairs = {
+        "lap2": (R.laplacian(2), R.laplacian(2)),
+        "lap2_4th": (R.laplacian(2, True), R.laplacian(2, True)),
+        "lap3": (R.laplacian(3), R.laplacian(3)),
+        "fwd": (R.embed(R.forward_first(), 0, 2), R.embed(R.forward_second(), 1, 2)),
+        "mixed": (R.embed(R.central_first_4th(), 0, 2), R.laplacian(2)),
+    }
+    a, b = pairs[name]
+    got = native.compose_stencil(_lib_stencil(native, a), _lib_stencil(native, b))
+    assert _as_rational(native, got) == R.compose(b, a)
+
+
+def test_library_stencil_builders(native):
+    from paper_2205_03354_amd import stencils
+
+    assert _as_rational(native, stencils.laplacian(2)) == R.laplacian(2)
+    assert _as_rational(native, stencils.laplacian(3, True)) == R.laplacian(3, True)
+    assert _as_rational(native, stencils.biharmonic(2)) == R.biharmonic(2)
+    assert _as_rational(native, stencils.biharmonic(3)) == R.biharmonic(3)
+    assert _as_rational(native, stencils.biharmonic(2, True)) == R.biharmonic(2, True)
+    assert stencils.biharmonic(2, True).radius == 4
+
+
+def test_lincomb_matches_oracle(native):
+    L = R.laplacian(2)
+    LL = R.compose(L, L)
+    I = R.identity(2)
+    lib_L = _lib_stencil(native, L)
+    lib_LL = _lib_stencil(native, LL)
+    lib_I = _lib_stencil(native, I)
+    got = native.stencil_lincomb([(1, 1, 0, lib_I), (8, 5, 4, lib_LL), (-1, 5, 2, lib_L)])
+    expect = R.lincomb([(1, 0, I), (F(8, 5), 4, LL), (F(-1, 5), 2, L)])
+    assert _as_rational(native, got) == expect
+
+
+def test_duplicate_and_zero_taps_are_canonicalised(native):
+    s = native.Stencil.create(2, [(1, 0), (1, 0), (0, 0), (-1, 0)], [2, 2, 0, 4], 8, 2)
+    dim, offs, nums, den, hp = s.get()
+    assert dim == 2 and hp == 2
+    assert offs == [(-1, 0, 0), (1, 0, 0)] and nums == [1, 1] and den == 2
+
+
+def test_errors(native):
+    with pytest.raises(native.ScError) as e:
+        native.Stencil.create(2, [(0, 0)], [1], 0, 0)
+    assert e.value.status == native.SC_EINVAL
+    with pytest.raises(native.ScError) as e:
+        native.Stencil.create(4, [(0, 0)], [1], 1, 0)
+    assert e.value.status == native.SC_EINVAL
+    a = native.Stencil.create(2, [(0, 0)], [1], 1, 0)
+    b = native.Stencil.create(3, [(0, 0, 0)], [1], 1, 0)
+    with pytest.raises(native.ScError) as e:
+        native.compose_stencil(a, b)
+    assert e.value.status == native.SC_EINVAL
+    assert b"dimension" in native.lib.sc_last_error()
+
+
+def test_rational_overflow_is_reported(native):
+    big = native.Stencil.create(1, [(1,), (-1,)], [2 ** 40 + 1, -(2 ** 40 + 3)], 2 ** 40 + 7, 1)
+    s = big
+    with pytest.raises(native.ScError) as e:
+        for _ in range(4):
+            s = native.compose_stencil(s, big)
+    assert e.value.status == native.SC_EOVERFLOW
+
+
+def test_apply_validation_without_gpu(native):
+    # argument checks run before any device work: aliasing, shapes, halo
+    lap = native.Stencil.create(2, [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)], [-4, 1, 1, 1, 1], 1, 2)
+    g = native.SCGrid()
+    g.dim, g.halo, g.dtype = 2, 0, native.SC_F64
+    g.n[0], g.n[1], g.n[2] = 8, 8, 1
+    g.pitch[0], g.pitch[1] = 8, 0
+    g.data = 4096  # never dereferenced: validation fails first
+    rc = native.lib.sc_apply_composed(lap.handle, 1.0, ctypes.byref(g), ctypes.byref(g), 0, None)
+    assert rc == native.SC_EINVAL and b"overlap" in native.lib.sc_last_error()
+    o = native.SCGrid()
+    ctypes.pointer(o)[0] = g
+    o.n[0] = 9
+    o.data = 1 << 30
+    rc = native.lib.sc_apply_composed(lap.handle, 1.0, ctypes.byref(g), ctypes.byref(o), 0, None)
+    assert rc == native.SC_EINVAL
+    o.n[0] = 8
+    rc = native.lib.sc_apply_composed(lap.handle, 1.0, ctypes.byref(g), ctypes.byref(o), 1, None)
+    assert rc == native.SC_EINVAL and b"halo" in native.lib.sc_last_error()
+    g.pitch[0] = 4
+    rc = native.lib.sc_apply_composed(lap.handle, 1.0, ctypes.byref(g), ctypes.byref(o), 0, None)
+    assert rc == native.SC_EINVAL and b"pitch" in native.lib.sc_last_error()

@@ -1,0 +1,182 @@
+"""GPU parity of the Krylov solves (biharmonic BVP, Cahn-Hilliard step).
+
+Bars (from the arithmetic): the GPU solution's true relative residual,
+recomputed by the oracle's own FP64 apply, is <= the requested 1e-10; the
+distance to the oracle's CG solution is bounded by kappa * tol (the systems
+are SPD, the solution unique), checked as 1e-6 relative for the BVPs
+(kappa <= 3e6 at these sizes) and 1e-9 for the well-conditioned
+Cahn-Hilliard step (kappa ~ 105 / 234). Iteration counts are not compared.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic as S
+from oracle import capi
+from oracle import problems as OP
+from oracle import rational as R
+from tests.gpu_util import lib_stencil
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2205_03354_amd import _native
+
+    return _native
+
+
+def _gpu_bvp(native, dim, size, precision, tol=1e-10, **kw):
+    from paper_2205_03354_amd import stencils
+
+    bvp = S.biharmonic_bvp(dim, size)
+    f = torch.from_numpy(bvp.f).to(DEV)
+    g = torch.from_numpy(bvp.g).to(DEV)
+    u = torch.zeros_like(f)
+    st = native.solve_biharmonic(stencils.biharmonic(dim), bvp.h, f, u, g=g, g_halo=bvp.halo, tol=tol,
+                                 precision=precision, **kw)
+    return bvp, u.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("N", [17, 33, 65])
+@pytest.mark.parametrize("prec", ["f64", "f32ir"])
+def test_bvp2d_parity(native, N, prec):
+    precision = native.SC_PREC_F64 if prec == "f64" else native.SC_PREC_F32_IR
+    bvp, x, st = _gpu_bvp(native, 2, N, precision)
+    op = R.biharmonic(2)
+    b = OP.bvp_rhs(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    rel = OP.true_relres(op, x, b, capi.ZERO_RING, bvp.h)
+    assert rel <= 1e-10, rel
+    assert st.rel_residual <= 1e-10
+    xo, it, rel_o, rc = OP.bvp_solve(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    dx = np.max(np.abs(x - xo)) / np.max(np.abs(xo))
+    assert dx <= 1e-6, dx
+    e_gpu, e_or = np.max(np.abs(x - bvp.u)), np.max(np.abs(xo - bvp.u))
+    assert abs(e_gpu - e_or) <= 1e-3 * e_or
+
+
+def test_bvp2d_second_order_on_gpu(native):
+    errs, hs = [], []
+    for N in (17, 33, 65):
+        bvp, x, st = _gpu_bvp(native, 2, N, native.SC_PREC_F64)
+        errs.append(np.max(np.abs(x - bvp.u)))
+        hs.append(bvp.h)
+    rate = math.log(errs[1] / errs[2]) / math.log(hs[1] / hs[2])
+    assert abs(rate - 2) < 0.1
+
+
+@pytest.mark.parametrize("n", [7, 15, 31])
+@pytest.mark.parametrize("prec", ["f64", "f32ir"])
+def test_bvp3d_parity(native, n, prec):
+    precision = native.SC_PREC_F64 if prec == "f64" else native.SC_PREC_F32_IR
+    bvp, x, st = _gpu_bvp(native, 3, n, precision)
+    op = R.biharmonic(3)
+    b = OP.bvp_rhs(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert OP.true_relres(op, x, b, capi.ZERO_RING, bvp.h) <= 1e-10
+    xo, it, rel_o, rc = OP.bvp_solve(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert np.max(np.abs(x - xo)) / np.max(np.abs(xo)) <= 1e-6
+
+
+def test_bvp_zero_ring_and_initial_guess(native):
+    # g = None (zero ring); starting from the oracle solution converges at once
+    from paper_2205_03354_amd import stencils
+
+    n = 40
+    f_np = S.uniform_field((n, n + 3), seed=8)
+    op = R.biharmonic(2)
+    xo, it, rel, rc = capi.cg(op, f_np, None, capi.ZERO_RING, 1e-12)
+    f = torch.from_numpy(f_np).to(DEV)
+    u = torch.zeros_like(f)
+    st = native.solve_biharmonic(stencils.biharmonic(2), 1.0, f, u, tol=1e-10)
+    x = u.cpu().numpy()
+    assert OP.true_relres(op, x, f_np, capi.ZERO_RING, 1.0) <= 1e-10
+    u2 = torch.from_numpy(xo).to(DEV)
+    st2 = native.solve_biharmonic(stencils.biharmonic(2), 1.0, f, u2, tol=1e-10)
+    assert st2.iterations == 0
+
+
+def test_bvp_deterministic(native):
+    _, x1, s1 = _gpu_bvp(native, 2, 33, native.SC_PREC_F64)
+    _, x2, s2 = _gpu_bvp(native, 2, 33, native.SC_PREC_F64)
+    assert np.array_equal(x1, x2) and s1.iterations == s2.iterations
+
+
+def test_breakdown_and_not_converged(native):
+    from paper_2205_03354_amd import stencils
+
+    n = 16
+    f = torch.from_numpy(S.uniform_field((n, n), seed=1)).to(DEV)
+    neg = native.stencil_lincomb([(-1, 1, 0, stencils.biharmonic(2))])  # negative definite
+    u = torch.zeros_like(f)
+    st = native.solve_biharmonic(neg, 1.0, f, u, raise_on_error=False)
+    assert st.status == native.SC_EBREAKDOWN
+    u = torch.zeros_like(f)
+    st = native.solve_biharmonic(stencils.biharmonic(2), 1.0, f, u, max_iter=5, check_every=2,
+                                 raise_on_error=False)
+    assert st.status == native.SC_ENOTCONV and 5 <= st.iterations <= 6 and st.rel_residual > 1e-10
+
+
+def _ch_gpu(native, u_np, h, eps, dt, Sst, steps, precision, tol=1e-10):
+    from paper_2205_03354_amd import stencils
+
+    u = torch.from_numpy(u_np).to(DEV)
+    L = stencils.laplacian(u_np.ndim)
+    stats = []
+    for _ in range(steps):
+        stats.append(native.ch_step(L, u, h, eps, dt, Sst, tol=tol, precision=precision))
+    return u.cpu().numpy(), stats
+
+
+@pytest.mark.parametrize("dim,N", [(2, 64), (3, 16)])
+@pytest.mark.parametrize("prec", ["f64", "f32ir"])
+def test_ch_step_parity(native, dim, N, prec):
+    precision = native.SC_PREC_F64 if prec == "f64" else native.SC_PREC_F32_IR
+    h = 1.0 / N
+    eps, dt, Sst = 4 * h, 0.1 * h * h, 2.0
+    u0 = S.zero_mean_uniform((N,) * dim, seed=3)
+    ug, _ = _ch_gpu(native, u0, h, eps, dt, Sst, 3, precision)
+    uo = u0
+    for _ in range(3):
+        uo, it, rel, rc = OP.ch_step(uo, h, eps, dt, Sst)
+    assert np.max(np.abs(ug - uo)) <= 1e-9 * max(1.0, np.max(np.abs(uo)))
+
+
+def test_ch_single_mode_closed_form_gpu(native):
+    from tests.test_oracle_numeric import _ch_mode_closed_form
+
+    N = 32
+    h = 1.0 / N
+    eps, dt, Sst = 4 * h, 0.1 * h * h, 2.0
+    u0, expect = _ch_mode_closed_form(0.3, N, (2, 1), eps, dt, Sst)
+    ug, _ = _ch_gpu(native, u0, h, eps, dt, Sst, 1, native.SC_PREC_F64, tol=1e-14)
+    assert np.max(np.abs(ug - expect)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32ir"])
+def test_ch_mass_energy_gpu(native, prec):
+    precision = native.SC_PREC_F64 if prec == "f64" else native.SC_PREC_F32_IR
+    N = 128
+    h = 1.0 / N
+    eps, dt, Sst = 4 * h, 0.1 * h * h, 2.0
+    u0 = S.zero_mean_uniform((N, N), seed=9)
+    from paper_2205_03354_amd import stencils
+
+    u = torch.from_numpy(u0).to(DEV)
+    L = stencils.laplacian(2)
+    m0, E0 = native.grid_diagnostics(u, h, eps)
+    assert abs(m0 - OP.mass(u0, h)) <= 1e-15
+    assert abs(E0 - OP.ch_energy(u0, h, eps)) <= 1e-12 * abs(E0)
+    E_prev = E0
+    for _ in range(20):
+        native.ch_step(L, u, h, eps, dt, Sst, precision=precision)
+        m, E = native.grid_diagnostics(u, h, eps)
+        assert abs(m - m0) <= 1e-12
+        assert E <= E_prev + 1e-14 * abs(E_prev)
+        E_prev = E
+    assert E_prev < E0
