@@ -436,7 +436,8 @@ sc_status apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_gr
 
 namespace {
 
-sc_status init_ctx(Ctx& c, hipStream_t st, const KStencil& ks, const int64_t* n, VecGuard& g) {
+sc_status init_ctx(Ctx& c, hipStream_t st, const KStencil& ks, const int64_t* n, VecGuard& g,
+                   const KStencil* ks2 = nullptr) {
   c.st = st;
   DevScalars* h = pinned_scalars();
   if (!h) {
@@ -459,6 +460,10 @@ sc_status init_ctx(Ctx& c, hipStream_t st, const KStencil& ks, const int64_t* n,
   for (int dt : {SC_F64, SC_F32}) {
     SweepLaunch L = sweep_on(K_CGDIR, ks, true, dt, n);
     slots = std::max(slots, sweep_blocks(L));
+    if (ks2) {
+      SweepLaunch L2 = sweep_on(K_CGDIR, *ks2, true, dt, n);
+      slots = std::max(slots, sweep_blocks(L2));
+    }
   }
   void* p = pool_alloc((size_t)slots * 3 * sizeof(double));
   if (!p) {
@@ -606,7 +611,7 @@ sc_status ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_solve
   VecGuard g;
   g.st = st;
   Ctx c;
-  if ((r = init_ctx(c, st, ksA, n, g)) != SC_OK) return r;
+  if ((r = init_ctx(c, st, ksA, n, g, &ksL)) != SC_OK) return r;
   DevVec x, b;
   if ((r = make_vec(dim, n, 0, SC_F64, st, &x, &g)) != SC_OK) return r;
   if ((r = make_vec(dim, n, 0, SC_F64, st, &b, &g)) != SC_OK) return r;
