@@ -18,28 +18,37 @@
 
 namespace sc {
 
-#define SC_CASE2(T, KIND, PER, P, RR) \
-  case P * 16 + RR: return run2d<T, KIND, P, RR, PER, 128>(L, st);
+#define SC_KEY2(P, RR, S) ((S) * 256 + (P) * 16 + (RR))
+#define SC_CASE2(T, KIND, PER, P, RR, S) \
+  case SC_KEY2(P, RR, S): return run2d<T, KIND, P, RR, PER, S>(L, st);
 #define SC_CASE3(T, KIND, PER, P, RR) \
   case P * 16 + RR: return run3d<T, KIND, P, RR, PER, 256>(L, st);
 
-#define SC_APPLY2D_SET(T, PER)               \
-  SC_CASE2(T, K_APPLY, PER, PAT_CROSS, 1)    \
-  SC_CASE2(T, K_APPLY, PER, PAT_CROSS, 2)    \
-  SC_CASE2(T, K_APPLY, PER, PAT_DIAMOND, 2)  \
-  SC_CASE2(T, K_APPLY, PER, PAT_CROSSBOX, 4) \
-  SC_CASE2(T, K_APPLY, PER, PAT_BOX, 1)      \
-  SC_CASE2(T, K_APPLY, PER, PAT_BOX, 2)      \
-  SC_CASE2(T, K_APPLY, PER, PAT_BOX, 3)      \
-  SC_CASE2(T, K_APPLY, PER, PAT_BOX, 4)
+// 2D plain apply: symmetric variants of the hot operators, generic kernels
+// for every pattern (any stencil of radius <= 4 has a kernel).
+#define SC_APPLY2D_SET(T, PER)                     \
+  SC_CASE2(T, K_APPLY, PER, PAT_CROSS, 1, true)    \
+  SC_CASE2(T, K_APPLY, PER, PAT_CROSS, 2, true)    \
+  SC_CASE2(T, K_APPLY, PER, PAT_DIAMOND, 2, true)  \
+  SC_CASE2(T, K_APPLY, PER, PAT_CROSSBOX, 4, true) \
+  SC_CASE2(T, K_APPLY, PER, PAT_CROSS, 1, false)    \
+  SC_CASE2(T, K_APPLY, PER, PAT_CROSS, 2, false)    \
+  SC_CASE2(T, K_APPLY, PER, PAT_DIAMOND, 2, false)  \
+  SC_CASE2(T, K_APPLY, PER, PAT_CROSSBOX, 4, false) \
+  SC_CASE2(T, K_APPLY, PER, PAT_BOX, 1, false)      \
+  SC_CASE2(T, K_APPLY, PER, PAT_BOX, 2, false)      \
+  SC_CASE2(T, K_APPLY, PER, PAT_BOX, 3, false)      \
+  SC_CASE2(T, K_APPLY, PER, PAT_BOX, 4, false)
 
-#define SC_SOLVE2D_SET(T, KIND, PER)      \
-  SC_CASE2(T, KIND, PER, PAT_CROSS, 1)    \
-  SC_CASE2(T, KIND, PER, PAT_CROSS, 2)    \
-  SC_CASE2(T, KIND, PER, PAT_DIAMOND, 2)  \
-  SC_CASE2(T, KIND, PER, PAT_CROSSBOX, 4) \
-  SC_CASE2(T, KIND, PER, PAT_BOX, 1)      \
-  SC_CASE2(T, KIND, PER, PAT_BOX, 2)
+// 2D solver sweeps: symmetric operators of the hot patterns, plus generic
+// radius-1/2 boxes for any other (point-symmetric) operator.
+#define SC_SOLVE2D_SET(T, KIND, PER)            \
+  SC_CASE2(T, KIND, PER, PAT_CROSS, 1, true)    \
+  SC_CASE2(T, KIND, PER, PAT_CROSS, 2, true)    \
+  SC_CASE2(T, KIND, PER, PAT_DIAMOND, 2, true)  \
+  SC_CASE2(T, KIND, PER, PAT_CROSSBOX, 4, true) \
+  SC_CASE2(T, KIND, PER, PAT_BOX, 1, false)     \
+  SC_CASE2(T, KIND, PER, PAT_BOX, 2, false)
 
 #define SC_APPLY3D_SET(T, PER)              \
   SC_CASE3(T, K_APPLY, PER, PAT_CROSS, 1)   \
@@ -53,7 +62,7 @@ namespace sc {
   SC_CASE3(T, KIND, PER, PAT_DIAMOND, 2) \
   SC_CASE3(T, KIND, PER, PAT_BOX, 1)
 
-#define SC_KEY (L.ks->pat * 16 + L.ks->R)
+#define SC_KEY (L.ks->dim == 2 ? SC_KEY2(L.ks->pat, L.ks->R, L.ks->sym ? 1 : 0) : (L.ks->pat * 16 + L.ks->R))
 
 #if SC_PART == 0
 hipError_t part_apply2d_f64(const SweepLaunch& L, hipStream_t st) {
@@ -81,8 +90,8 @@ hipError_t part_solve2d_f64_periodic(const SweepLaunch& L, hipStream_t st) {
     case K_RESID: switch (SC_KEY) { SC_SOLVE2D_SET(double, K_RESID, true) default: break; } break;
     case K_CHRHS:
       switch (SC_KEY) {
-        SC_CASE2(double, K_CHRHS, true, PAT_CROSS, 1)
-        SC_CASE2(double, K_CHRHS, true, PAT_CROSS, 2)
+        SC_CASE2(double, K_CHRHS, true, PAT_CROSS, 1, true)
+        SC_CASE2(double, K_CHRHS, true, PAT_CROSS, 2, true)
         default: break;
       }
       break;

@@ -50,8 +50,13 @@ struct KStencil {
   int pat = 0;
   int R = 0;
   int ntaps = 0;
+  bool sym = false;  // w(dx,dy,dz) unchanged by negating any one component
   double w[kMaxTaps] = {};
 };
+
+// The same weights re-indexed for the BOX pattern of the same radius
+// (sym cleared): the fallback for a (kind, pattern) without its own kernel.
+KStencil to_box(const KStencil& ks);
 
 // Choose the cheapest instantiated (pattern, radius) containing every tap of
 // the (already scaled) stencil given by offsets and weights.
@@ -79,6 +84,7 @@ struct SweepLaunch {
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   int flag = 0;
   bool vec_store = false;
+  bool in_aligned = false;  // in / in2 / aux rows start on 16-byte boundaries
 };
 
 // Number of blocks (= partial-sum slots) the sweep will launch.

@@ -8,15 +8,16 @@
 
 namespace sc {
 
-// Output rows (2D) per tile: aim at >= ~2048 blocks (8 per CU) without
-// making tiles so short that the 2R halo rows dominate.
-inline int tile_rows_2d(int64_t n1, int64_t tiles_x, int R) {
+// Output rows (2D) per tile: aim at ~5600 one-wave tiles (about 22 per CU,
+// more than can be resident, so the tail is short) without making tiles so
+// short that the 2R halo rows dominate.
+inline int tile_rows_2d(int64_t n1, int64_t strips, int R) {
   if (const char* e = std::getenv("SCOMP_TY2D")) {
     const int v = std::atoi(e);
     if (v > 0) return v;
   }
-  int64_t ty = (n1 * tiles_x + 2047) / 2048;
-  const int64_t lo = 8 * R > 16 ? 8 * R : 16;
+  int64_t ty = (n1 * strips + 5599) / 5600;
+  const int64_t lo = 4 * R > 12 ? 4 * R : 12;
   if (ty < lo) ty = lo;
   if (ty > n1) ty = n1;
   if (ty < 1) ty = 1;
@@ -53,6 +54,8 @@ SweepArgs<T> make_args(const SweepLaunch& L) {
   a.c0 = L.c0; a.c1 = L.c1; a.c2 = L.c2;
   a.flag = L.flag;
   a.vec_store = L.vec_store ? 1 : 0;
+  a.in_aligned = L.in_aligned ? 1 : 0;
+  a.alt = 0;
   return a;
 }
 
@@ -63,18 +66,17 @@ Taps<T, N> make_taps(const KStencil& ks) {
   return t;
 }
 
-// Geometry of a 2D launch with NT threads per block.
-template <typename T, int NT>
+// Geometry of a 2D launch: one wave per tile, strips of 64 * VPL columns.
+template <typename T>
 inline void geom2d(const SweepLaunch& L, int R, SweepArgs<T>& a, int* blocks) {
-  constexpr int VEC = 16 / (int)sizeof(T);
-  const int64_t TX = (int64_t)NT * VEC;
-  const int64_t tx = (L.n[0] + TX - 1) / TX;
-  a.ty = tile_rows_2d(L.n[1], tx, R);
+  const int64_t TX = strip_width_2d<T>();
+  const int64_t strips = (L.n[0] + TX - 1) / TX;
+  a.ty = tile_rows_2d(L.n[1], strips, R);
   const int64_t ty = (L.n[1] + a.ty - 1) / a.ty;
-  a.tiles_a = (int)tx;
+  a.tiles_a = (int)strips;
   a.tiles_b = (int)ty;
   a.small = (L.n[0] < 2 * R + 8 || L.n[1] < 2 * R + 8) ? 1 : 0;
-  *blocks = (int)(tx * ty);
+  *blocks = (int)(strips * ty);
 }
 
 template <typename T, int NT>
@@ -92,14 +94,31 @@ inline void geom3d(const SweepLaunch& L, int R, SweepArgs<T>& a, int* blocks) {
   *blocks = a.tiles_a * a.tiles_b;
 }
 
-template <typename T, int KIND, int PAT, int R, bool PER, int NT>
+// Class weights (|dx|, |dy|) of a mirror-symmetric stencil.
+template <typename T, int PAT, int R>
+Taps<T, sym_num_classes(PAT, R)> make_sym_taps(const KStencil& ks) {
+  Taps<T, sym_num_classes(PAT, R)> t{};
+  for (int aa = 0; aa <= R; ++aa)
+    for (int d = 0; d <= R; ++d)
+      if (in_pattern(PAT, R, d, aa, 0)) t.w[sym_class_index(PAT, R, d, aa)] = (T)ks.w[tap_index(PAT, R, 2, d, aa, 0)];
+  return t;
+}
+
+template <typename T, int KIND, int PAT, int R, bool PER, bool SYM>
 hipError_t run2d(const SweepLaunch& L, hipStream_t st) {
   SweepArgs<T> a = make_args<T>(L);
   int blocks = 0;
-  geom2d<T, NT>(L, R, a, &blocks);
-  const auto taps = make_taps<T, num_taps(PAT, R, 2)>(*L.ks);
-  hipLaunchKernelGGL((sweep2d_kernel<T, KIND, PAT, R, PER, NT>), dim3(blocks), dim3(NT), 0, st, a,
-                     taps);
+  geom2d<T>(L, R, a, &blocks);
+  a.alt = SYM ? 1 : 0;
+  if (const char* e = std::getenv("SCOMP_NOALT"))
+    if (e[0] == '1') a.alt = 0;
+  if constexpr (SYM) {
+    const auto taps = make_sym_taps<T, PAT, R>(*L.ks);
+    hipLaunchKernelGGL((sweep2d_kernel<T, KIND, PAT, R, PER, true>), dim3(blocks), dim3(64), 0, st, a, taps);
+  } else {
+    const auto taps = make_taps<T, num_taps(PAT, R, 2)>(*L.ks);
+    hipLaunchKernelGGL((sweep2d_kernel<T, KIND, PAT, R, PER, false>), dim3(blocks), dim3(64), 0, st, a, taps);
+  }
   return hipGetLastError();
 }
 

@@ -10,10 +10,10 @@ int sweep_blocks(const SweepLaunch& L) {
   if (L.ks->dim == 2) {
     if (L.dtype == SC_F64) {
       SweepArgs<double> a{};
-      geom2d<double, 128>(L, R, a, &blocks);
+      geom2d<double>(L, R, a, &blocks);
     } else {
       SweepArgs<float> a{};
-      geom2d<float, 128>(L, R, a, &blocks);
+      geom2d<float>(L, R, a, &blocks);
     }
   } else {
     if (L.dtype == SC_F64) {
@@ -27,24 +27,40 @@ int sweep_blocks(const SweepLaunch& L) {
   return blocks;
 }
 
-hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
-  hipError_t e = hipErrorInvalidValue;
+namespace {
+
+hipError_t route(const SweepLaunch& L, hipStream_t st) {
   if (L.ks->dim == 2) {
-    if (L.kind == K_APPLY) {
-      e = L.dtype == SC_F64 ? part_apply2d_f64(L, st) : part_apply2d_f32(L, st);
-    } else if (L.dtype == SC_F32) {
-      e = part_solve2d_f32(L, st);
-    } else {
-      e = L.periodic ? part_solve2d_f64_periodic(L, st) : part_solve2d_f64_ring(L, st);
-    }
-  } else if (L.ks->dim == 3) {
-    if (L.kind == K_APPLY) {
-      e = part_apply3d(L, st);
-    } else if (L.dtype == SC_F32) {
-      e = part_solve3d_f32(L, st);
-    } else {
-      e = part_solve3d_f64(L, st);
-    }
+    if (L.kind == K_APPLY) return L.dtype == SC_F64 ? part_apply2d_f64(L, st) : part_apply2d_f32(L, st);
+    if (L.dtype == SC_F32) return part_solve2d_f32(L, st);
+    return L.periodic ? part_solve2d_f64_periodic(L, st) : part_solve2d_f64_ring(L, st);
+  }
+  if (L.ks->dim == 3) {
+    if (L.kind == K_APPLY) return part_apply3d(L, st);
+    if (L.dtype == SC_F32) return part_solve3d_f32(L, st);
+    return part_solve3d_f64(L, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+// Try the stencil's own (pattern, symmetry) kernel, then the generic kernel
+// of the same pattern, then the generic box of the same radius.
+hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
+  hipError_t e = route(L, st);
+  if (e == hipErrorInvalidValue && L.ks->sym) {
+    KStencil g = *L.ks;
+    g.sym = false;
+    SweepLaunch L2 = L;
+    L2.ks = &g;
+    e = route(L2, st);
+  }
+  if (e == hipErrorInvalidValue && L.ks->pat != PAT_BOX) {
+    const KStencil b = to_box(*L.ks);
+    SweepLaunch L3 = L;
+    L3.ks = &b;
+    e = route(L3, st);
   }
   if (e == hipErrorInvalidValue)
     set_error("no kernel instance for kind %d, %s, %s, %dD pattern %d radius %d", L.kind,

@@ -171,7 +171,18 @@ void set_out2(SweepLaunch& L, const DevVec& v) {
   L.zout2 = v.lay.zpitch;
 }
 
-sc_status launch(const SweepLaunch& L, hipStream_t st) {
+bool aligned16(const void* p, int64_t pitch, int64_t zpitch, int64_t es, bool three_d) {
+  if (!p) return true;
+  return (uintptr_t)p % 16 == 0 && (pitch * es) % 16 == 0 && (!three_d || (zpitch * es) % 16 == 0);
+}
+
+// Launch a sweep after deriving the alignment flags from its pointers.
+sc_status launch(SweepLaunch L, hipStream_t st) {
+  const int64_t es = (int64_t)esize(L.dtype);
+  const bool d3 = L.ks->dim == 3;
+  L.in_aligned = aligned16(L.in, L.pin, L.zin, es, d3) && aligned16(L.in2, L.pin2, L.zin2, es, d3) &&
+                 aligned16(L.aux, L.paux, L.zaux, es, d3);
+  L.vec_store = aligned16(L.out, L.pout, L.zout, es, d3) && aligned16(L.out2, L.pout2, L.zout2, es, d3);
   const hipError_t e = launch_sweep(L, st);
   if (e == hipErrorInvalidValue) return SC_EUNSUPPORTED;
   if (e != hipSuccess) {
@@ -428,9 +439,6 @@ sc_status apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_gr
   L.out = interior(out);
   L.pout = out->pitch[0];
   L.zout = out->pitch[1];
-  const int64_t es = (int64_t)esize(out->dtype);
-  L.vec_store = ((uintptr_t)L.out % 16 == 0) && ((out->pitch[0] * es) % 16 == 0) &&
-                (out->dim == 2 || (out->pitch[1] * es) % 16 == 0);
   return launch(L, st);
 }
 

@@ -254,8 +254,36 @@ sc_status make_kstencil(int dim, const std::vector<std::array<int32_t, 3>>& off,
     const int idx = tap_index(ks.pat, ks.R, dim, off[t][0], off[t][1], dim == 3 ? off[t][2] : 0);
     ks.w[idx] = (double)w[t];
   }
+  // mirror symmetry: negating any one offset component keeps the weight
+  ks.sym = true;
+  const int zr = dim == 3 ? ks.R : 0;
+  for (int z = -zr; z <= zr && ks.sym; ++z)
+    for (int y = -ks.R; y <= ks.R && ks.sym; ++y)
+      for (int x = -ks.R; x <= ks.R && ks.sym; ++x) {
+        if (!in_pattern(ks.pat, ks.R, x, y, z)) continue;
+        const double v = ks.w[tap_index(ks.pat, ks.R, dim, x, y, z)];
+        if (v != ks.w[tap_index(ks.pat, ks.R, dim, -x, y, z)] || v != ks.w[tap_index(ks.pat, ks.R, dim, x, -y, z)] ||
+            v != ks.w[tap_index(ks.pat, ks.R, dim, x, y, -z)])
+          ks.sym = false;
+      }
   *out = ks;
   return SC_OK;
+}
+
+KStencil to_box(const KStencil& ks) {
+  KStencil b;
+  b.dim = ks.dim;
+  b.pat = PAT_BOX;
+  b.R = ks.R;
+  b.ntaps = num_taps(PAT_BOX, ks.R, ks.dim);
+  b.sym = false;
+  const int zr = ks.dim == 3 ? ks.R : 0;
+  for (int z = -zr; z <= zr; ++z)
+    for (int y = -ks.R; y <= ks.R; ++y)
+      for (int x = -ks.R; x <= ks.R; ++x)
+        if (in_pattern(ks.pat, ks.R, x, y, z))
+          b.w[tap_index(PAT_BOX, ks.R, ks.dim, x, y, z)] = ks.w[tap_index(ks.pat, ks.R, ks.dim, x, y, z)];
+  return b;
 }
 
 sc_status make_kstencil(const sc_stencil* s, double h, KStencil* out) {
