@@ -24,7 +24,9 @@
  *   only launch work (sc_apply_composed) are asynchronous on that stream;
  *   solver calls (sc_solve_biharmonic, sc_ch_step, sc_grid_diagnostics)
  *   return after their work on that stream has completed, because they
- *   test convergence on the host.
+ *   test convergence on the host. A solver call made on the NULL stream runs
+ *   on a per-thread library stream that first waits for the NULL stream's
+ *   queued work (the NULL stream cannot be captured into a hipGraph).
  * - Weights are exact rationals: weight k is num[k] / (den * h^p) where p is
  *   the stencil's power of h (its derivative order). They are converted to
  *   the grid's floating type once, per call.
@@ -49,7 +51,8 @@ typedef enum sc_status {
   SC_ENOMEM = 4,       /* device workspace could not be allocated */
   SC_ENOTCONV = 5,     /* iteration limit reached; statistics are filled */
   SC_EBREAKDOWN = 6,   /* CG breakdown: p.Ap <= 0 or not finite */
-  SC_EUNSUPPORTED = 7  /* valid request outside what the kernels implement */
+  SC_EUNSUPPORTED = 7, /* valid request outside what the kernels implement */
+  SC_ECANCELLED = 8    /* request cancelled before it finished */
 } sc_status;
 
 typedef enum sc_dtype { SC_F64 = 0, SC_F32 = 1 } sc_dtype;
@@ -171,6 +174,8 @@ typedef struct sc_solve_opts {
   int32_t precision;    /* sc_precision */
   double inner_tol;     /* SC_PREC_F32_IR: residual reduction asked of each FP32 solve */
   int32_t check_every;  /* CG iterations launched between host convergence checks */
+  int32_t use_graph;    /* 1: replay each block of check_every iterations from a
+                           captured hipGraph (check_every even); 0: plain launches */
 } sc_solve_opts;
 
 typedef struct sc_solve_stats {
@@ -182,7 +187,7 @@ typedef struct sc_solve_stats {
 } sc_solve_stats;
 
 /* Fill opts with defaults: tol 1e-10, max_iter 10^7, SC_PREC_F64,
- * inner_tol 1e-4, check_every 64. */
+ * inner_tol 1e-4, check_every 64, use_graph 1. */
 void sc_solve_opts_default(sc_solve_opts* opts);
 
 /*
@@ -242,6 +247,89 @@ sc_status sc_ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_so
  */
 sc_status sc_grid_diagnostics(const sc_grid* u, double h, double eps, double* mass,
                               double* energy, sc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Request server: continuous batching of solves
+ *
+ * A server owns a worker thread, `max_slots` HIP streams and a device-memory
+ * budget. Submitted requests are copied and queued; the worker admits them
+ * in arrival order whenever a slot is free and their device footprint fits
+ * the budget, keeps their whole solver state resident on the device, and
+ * advances every admitted request by blocks of check_every CG iterations
+ * (each block one hipGraph replay on the request's own stream), so requests
+ * that arrive while others run join at the next block boundary and their
+ * kernels overlap on the GPU. Finished requests are copied back and retired,
+ * which frees their slot and budget for the next ones. Each request computes
+ * exactly what the blocking entry point would: results are bit-identical
+ * whether a request runs alone or in a mix.
+ * ------------------------------------------------------------------------- */
+
+typedef struct sc_server sc_server;
+
+typedef enum sc_request_kind { SC_REQ_BVP = 0, SC_REQ_CH_STEP = 1 } sc_request_kind;
+
+typedef struct sc_server_opts {
+  uint64_t hbm_budget;   /* device bytes for request state; 0 = 80% of the free memory */
+  int32_t max_slots;     /* requests resident on the device at once (1..256) */
+  sc_solve_opts solve;   /* solver options for every request */
+  int32_t fake_device;   /* 1: run the scheduler with no device work (testing) */
+} sc_server_opts;
+
+/*
+ * One request. Host arrays are contiguous FP64 with x fastest and are copied
+ * at submit (the caller may reuse them at once); u_out must stay valid until
+ * the request's result has been polled.
+ *   SC_REQ_BVP:     op = composed operator; f = forcing on the n unknowns;
+ *                   g = ring values on the (n + 2 radius) box or NULL (zero
+ *                   ring); u0 = initial guess or NULL (zero).
+ *   SC_REQ_CH_STEP: op = the Laplacian; u0 = u^n (periodic); ch = step
+ *                   parameters; f, g unused.
+ *   precision       sc_precision for this request, or -1 for the server's.
+ */
+typedef struct sc_request {
+  int32_t kind;
+  int32_t dim;
+  int64_t n[3];
+  double h;
+  const sc_stencil* op;
+  const double* f;
+  const double* g;
+  const double* u0;
+  double* u_out;
+  sc_ch_params ch;
+  int32_t precision;
+} sc_request;
+
+typedef struct sc_result {
+  uint64_t id;
+  int32_t status;        /* the solve's sc_status; SC_ECANCELLED; SC_ENOMEM if the
+                            request can never fit the budget */
+  int64_t iterations;
+  int32_t outer;
+  double rel_residual;
+  double t_submit;       /* seconds since server creation */
+  double t_admit;
+  double t_done;
+  uint64_t device_bytes; /* footprint charged to the budget */
+} sc_result;
+
+/* Create a server and start its worker. Errors: SC_EINVAL, SC_EDEVICE. */
+sc_status sc_server_create(const sc_server_opts* opts, sc_server** out);
+/* Queue a request; *id identifies its result. Errors: SC_EINVAL (shape,
+ * stencil, missing arrays), SC_EUNSUPPORTED. */
+sc_status sc_server_submit(sc_server* s, const sc_request* r, uint64_t* id);
+/* Move up to `max` finished results into out[0..*n); waits up to wait_ms
+ * for the first one when none is ready. */
+sc_status sc_server_poll(sc_server* s, sc_result* out, int32_t max, int32_t* n, int32_t wait_ms);
+/* Cancel a queued or running request (its result reports SC_ECANCELLED);
+ * SC_EINVAL if the id is unknown or already finished. */
+sc_status sc_server_cancel(sc_server* s, uint64_t id);
+/* Requests queued, resident on the device, and finished-but-unpolled. */
+sc_status sc_server_load(sc_server* s, int32_t* queued, int32_t* active, int32_t* finished,
+                         uint64_t* device_bytes);
+/* Stop the worker after the resident requests finish; queued ones are
+ * cancelled; unpolled results are discarded. */
+void sc_server_destroy(sc_server* s);
 
 /* ---------------------------------------------------------------------------
  * Errors and version

@@ -7,11 +7,15 @@ The public calls mirror the C ABI in ``include/scomp.h``:
 """
 
 from ._native import (  # noqa: F401
+    ApplyPlan,
     SC_BC_HALO,
     SC_BC_PERIODIC,
     SC_PREC_F32_IR,
     SC_PREC_F64,
+    SC_REQ_BVP,
+    SC_REQ_CH_STEP,
     ScError,
+    Server,
     SolveStats,
     Stencil,
     apply_composed,

@@ -16,7 +16,9 @@ from typing import Optional, Sequence, Tuple
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libscomp.so")
 
-SC_OK, SC_EINVAL, SC_EOVERFLOW, SC_EDEVICE, SC_ENOMEM, SC_ENOTCONV, SC_EBREAKDOWN, SC_EUNSUPPORTED = range(8)
+(SC_OK, SC_EINVAL, SC_EOVERFLOW, SC_EDEVICE, SC_ENOMEM, SC_ENOTCONV, SC_EBREAKDOWN, SC_EUNSUPPORTED,
+ SC_ECANCELLED) = range(9)
+SC_REQ_BVP, SC_REQ_CH_STEP = 0, 1
 SC_F64, SC_F32 = 0, 1
 SC_BC_PERIODIC, SC_BC_HALO = 0, 1
 SC_PREC_F64, SC_PREC_F32_IR = 0, 1
@@ -25,7 +27,8 @@ EXPORTED = (
     "sc_stencil_create", "sc_compose_stencil", "sc_stencil_lincomb", "sc_stencil_get",
     "sc_stencil_radius", "sc_stencil_free", "sc_apply_composed", "sc_solve_opts_default",
     "sc_solve_biharmonic", "sc_ch_step", "sc_grid_diagnostics", "sc_status_str",
-    "sc_last_error", "sc_version",
+    "sc_last_error", "sc_version", "sc_server_create", "sc_server_submit", "sc_server_poll",
+    "sc_server_cancel", "sc_server_load", "sc_server_destroy",
 )
 
 
@@ -42,7 +45,7 @@ class SCGrid(ctypes.Structure):
 
 class SCSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("precision", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class SCSolveStats(ctypes.Structure):
@@ -52,6 +55,23 @@ class SCSolveStats(ctypes.Structure):
 
 class SCChParams(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("eps", ctypes.c_double), ("dt", ctypes.c_double), ("S", ctypes.c_double)]
+
+
+class SCServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_slots", ctypes.c_int32), ("solve", SCSolveOpts),
+                ("fake_device", ctypes.c_int32)]
+
+
+class SCRequest(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dim", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double),
+                ("op", ctypes.c_void_p), ("f", ctypes.c_void_p), ("g", ctypes.c_void_p), ("u0", ctypes.c_void_p),
+                ("u_out", ctypes.c_void_p), ("ch", SCChParams), ("precision", ctypes.c_int32)]
+
+
+class SCResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("iterations", ctypes.c_int64),
+                ("outer", ctypes.c_int32), ("rel_residual", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("device_bytes", ctypes.c_uint64)]
 
 
 def _load() -> ctypes.CDLL:
@@ -78,6 +98,16 @@ def _load() -> ctypes.CDLL:
     L.sc_ch_step.argtypes = [P, ctypes.POINTER(SCChParams), ctypes.POINTER(SCSolveOpts),
                              ctypes.POINTER(SCGrid), ctypes.POINTER(SCSolveStats), P]
     L.sc_grid_diagnostics.argtypes = [ctypes.POINTER(SCGrid), D, D, P, P, P]
+    L.sc_server_create.argtypes = [ctypes.POINTER(SCServerOpts), PP]
+    L.sc_server_submit.argtypes = [P, ctypes.POINTER(SCRequest), ctypes.POINTER(ctypes.c_uint64)]
+    L.sc_server_poll.argtypes = [P, ctypes.POINTER(SCResult), I32, ctypes.POINTER(ctypes.c_int32), I32]
+    L.sc_server_cancel.argtypes = [P, ctypes.c_uint64]
+    L.sc_server_load.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]
+    L.sc_server_destroy.argtypes = [P]
+    L.sc_server_destroy.restype = None
+    for name in ("sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_cancel", "sc_server_load"):
+        getattr(L, name).restype = ctypes.c_int
     L.sc_status_str.argtypes = [ctypes.c_int]
     L.sc_status_str.restype = ctypes.c_char_p
     L.sc_last_error.argtypes = []
@@ -212,6 +242,30 @@ def apply_composed(st: Stencil, x, y, bc: int = SC_BC_PERIODIC, h: float = 1.0, 
     return y
 
 
+class ApplyPlan:
+    """A pre-marshalled y = S x launch for repeated use on fixed buffers:
+    the grid descriptors and stream are built once, each call only crosses
+    the C ABI."""
+
+    def __init__(self, st: Stencil, x, y, bc: int = SC_BC_PERIODIC, h: float = 1.0, halo: int = 0,
+                 out_halo: Optional[int] = None, stream=None):
+        self._st = st
+        self._gi = grid_of(x, halo)
+        self._go = grid_of(y, halo if out_halo is None else out_halo)
+        self._keep = (x, y)
+        self._h = float(h)
+        self._bc = int(bc)
+        self._stream = _stream(stream)
+        self._fn = lib.sc_apply_composed
+        self._args = (st.handle, ctypes.c_double(self._h), ctypes.byref(self._gi), ctypes.byref(self._go),
+                      self._bc, self._stream)
+
+    def __call__(self):
+        rc = self._fn(*self._args)
+        if rc != SC_OK:
+            _check(rc)
+
+
 @dataclass
 class SolveStats:
     iterations: int
@@ -222,7 +276,7 @@ class SolveStats:
     status: int
 
 
-def _opts(tol, max_iter, precision, inner_tol, check_every) -> SCSolveOpts:
+def _opts(tol, max_iter, precision, inner_tol, check_every, use_graph=True) -> SCSolveOpts:
     o = SCSolveOpts()
     lib.sc_solve_opts_default(ctypes.byref(o))
     o.tol = tol
@@ -230,6 +284,7 @@ def _opts(tol, max_iter, precision, inner_tol, check_every) -> SCSolveOpts:
     o.precision = int(precision)
     o.inner_tol = inner_tol
     o.check_every = int(check_every)
+    o.use_graph = 1 if use_graph else 0
     return o
 
 
@@ -239,11 +294,12 @@ def _stats(s: SCSolveStats, status: int) -> SolveStats:
 
 def solve_biharmonic(op: Stencil, h: float, f, u, g=None, g_halo: int = 0, tol: float = 1e-10,
                      max_iter: int = 10**7, precision: int = SC_PREC_F64, inner_tol: float = 1e-4,
-                     check_every: int = 64, raise_on_error: bool = True, stream=None) -> SolveStats:
+                     check_every: int = 64, use_graph: bool = True, raise_on_error: bool = True,
+                     stream=None) -> SolveStats:
     """A u = f at the unknowns with the ring prescribed by g (see scomp.h)."""
     gf, gu = grid_of(f, 0), grid_of(u, 0)
     gg = ctypes.byref(grid_of(g, g_halo)) if g is not None else None
-    o = _opts(tol, max_iter, precision, inner_tol, check_every)
+    o = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph)
     st = SCSolveStats()
     status = lib.sc_solve_biharmonic(op.handle, float(h), ctypes.byref(gf), gg, ctypes.byref(o), ctypes.byref(gu),
                                      ctypes.byref(st), _stream(stream))
@@ -254,11 +310,12 @@ def solve_biharmonic(op: Stencil, h: float, f, u, g=None, g_halo: int = 0, tol: 
 
 def ch_step(lap: Stencil, u, h: float, eps: float, dt: float, S: float, tol: float = 1e-10,
             max_iter: int = 10**6, precision: int = SC_PREC_F64, inner_tol: float = 1e-4,
-            check_every: int = 32, raise_on_error: bool = True, stream=None) -> SolveStats:
+            check_every: int = 32, use_graph: bool = True, raise_on_error: bool = True,
+            stream=None) -> SolveStats:
     """One linearly stabilised semi-implicit Cahn-Hilliard step, in place on u."""
     gu = grid_of(u, 0)
     prm = SCChParams(h, eps, dt, S)
-    o = _opts(tol, max_iter, precision, inner_tol, check_every)
+    o = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph)
     st = SCSolveStats()
     status = lib.sc_ch_step(lap.handle, ctypes.byref(prm), ctypes.byref(o), ctypes.byref(gu), ctypes.byref(st),
                             _stream(stream))
@@ -274,6 +331,111 @@ def grid_diagnostics(u, h: float, eps: float, stream=None) -> Tuple[float, float
     _check(lib.sc_grid_diagnostics(ctypes.byref(gu), float(h), float(eps), ctypes.byref(m), ctypes.byref(e),
                                    _stream(stream)))
     return m.value, e.value
+
+
+class Server:
+    """Continuous-batching request server (see sc_server_* in scomp.h).
+
+    Host arrays are numpy FP64 with x as the last axis; each submit returns
+    the request id, and the solution lands in the array returned by
+    ``result_array(id)`` once its result has been polled."""
+
+    def __init__(self, hbm_budget: int = 0, max_slots: int = 16, tol: float = 1e-10,
+                 precision: int = SC_PREC_F64, inner_tol: float = 1e-4, check_every: int = 64,
+                 use_graph: bool = True, max_iter: int = 10**7, fake_device: bool = False):
+        o = SCServerOpts()
+        o.hbm_budget = int(hbm_budget)
+        o.max_slots = int(max_slots)
+        o.solve = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph)
+        o.fake_device = 1 if fake_device else 0
+        h = ctypes.c_void_p()
+        _check(lib.sc_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._out = {}
+        self._keep = {}
+
+    def _submit(self, req: SCRequest, out, keep) -> int:
+        rid = ctypes.c_uint64()
+        _check(lib.sc_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._out[rid.value] = out
+        self._keep[rid.value] = keep
+        return rid.value
+
+    @staticmethod
+    def _shape(a):
+        n = list(a.shape)[::-1] + [1, 1]
+        return a.ndim, n[:3]
+
+    def submit_bvp(self, op: Stencil, h: float, f, g=None, u0=None, precision: int = -1) -> int:
+        import numpy as np
+
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        dim, n = self._shape(f)
+        out = np.zeros_like(f)
+        req = SCRequest()
+        req.kind, req.dim = SC_REQ_BVP, dim
+        for a in range(3):
+            req.n[a] = n[a]
+        req.h = float(h)
+        req.op = op.handle.value
+        req.f = f.ctypes.data
+        gg = np.ascontiguousarray(g, dtype=np.float64) if g is not None else None
+        uu = np.ascontiguousarray(u0, dtype=np.float64) if u0 is not None else None
+        req.g = gg.ctypes.data if gg is not None else None
+        req.u0 = uu.ctypes.data if uu is not None else None
+        req.u_out = out.ctypes.data
+        req.precision = int(precision)
+        return self._submit(req, out, (op, f, gg, uu))
+
+    def submit_ch(self, lap: Stencil, u0, h: float, eps: float, dt: float, S: float, precision: int = -1) -> int:
+        import numpy as np
+
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        dim, n = self._shape(u0)
+        out = np.zeros_like(u0)
+        req = SCRequest()
+        req.kind, req.dim = SC_REQ_CH_STEP, dim
+        for a in range(3):
+            req.n[a] = n[a]
+        req.h = float(h)
+        req.op = lap.handle.value
+        req.u0 = u0.ctypes.data
+        req.u_out = out.ctypes.data
+        req.ch = SCChParams(h, eps, dt, S)
+        req.precision = int(precision)
+        return self._submit(req, out, (lap, u0))
+
+    def poll(self, max_results: int = 256, wait_ms: int = 0):
+        buf = (SCResult * max_results)()
+        n = ctypes.c_int32()
+        _check(lib.sc_server_poll(self._h, buf, max_results, ctypes.byref(n), int(wait_ms)))
+        res = []
+        for i in range(n.value):
+            r = buf[i]
+            self._keep.pop(r.id, None)
+            res.append({"id": r.id, "status": r.status, "iterations": r.iterations, "outer": r.outer,
+                        "rel_residual": r.rel_residual, "t_submit": r.t_submit, "t_admit": r.t_admit,
+                        "t_done": r.t_done, "device_bytes": r.device_bytes})
+        return res
+
+    def result_array(self, rid: int):
+        return self._out.pop(rid)
+
+    def cancel(self, rid: int):
+        _check(lib.sc_server_cancel(self._h, rid))
+
+    def load(self):
+        q, a, f, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64()
+        _check(lib.sc_server_load(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(f), ctypes.byref(b)))
+        return {"queued": q.value, "active": a.value, "finished": f.value, "device_bytes": b.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.sc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def version() -> str:

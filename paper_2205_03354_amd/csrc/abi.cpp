@@ -104,6 +104,7 @@ void sc_solve_opts_default(sc_solve_opts* o) {
   o->precision = SC_PREC_F64;
   o->inner_tol = 1e-4;
   o->check_every = 64;
+  o->use_graph = 1;
 }
 
 sc_status sc_solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, const sc_grid* g,
@@ -122,6 +123,32 @@ sc_status sc_grid_diagnostics(const sc_grid* u, double h, double eps, double* ma
   SC_GUARD(return sc::grid_diagnostics(u, h, eps, mass, energy, reinterpret_cast<hipStream_t>(stream));)
 }
 
+sc_status sc_server_create(const sc_server_opts* opts, sc_server** out) {
+  SC_GUARD(return sc::server_create(opts, out);)
+}
+
+sc_status sc_server_submit(sc_server* s, const sc_request* r, uint64_t* id) {
+  SC_GUARD(return sc::server_submit(s, r, id);)
+}
+
+sc_status sc_server_poll(sc_server* s, sc_result* out, int32_t max, int32_t* n, int32_t wait_ms) {
+  SC_GUARD(return sc::server_poll(s, out, max, n, wait_ms);)
+}
+
+sc_status sc_server_cancel(sc_server* s, uint64_t id) { SC_GUARD(return sc::server_cancel(s, id);) }
+
+sc_status sc_server_load(sc_server* s, int32_t* queued, int32_t* active, int32_t* finished,
+                         uint64_t* device_bytes) {
+  SC_GUARD(return sc::server_load(s, queued, active, finished, device_bytes);)
+}
+
+void sc_server_destroy(sc_server* s) {
+  try {
+    sc::server_destroy(s);
+  } catch (...) {
+  }
+}
+
 const char* sc_status_str(sc_status s) {
   switch (s) {
     case SC_OK: return "ok";
@@ -132,6 +159,7 @@ const char* sc_status_str(sc_status s) {
     case SC_ENOTCONV: return "not converged";
     case SC_EBREAKDOWN: return "CG breakdown";
     case SC_EUNSUPPORTED: return "unsupported";
+    case SC_ECANCELLED: return "cancelled";
   }
   return "unknown status";
 }

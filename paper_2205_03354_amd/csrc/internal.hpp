@@ -6,6 +6,8 @@
 
 #include <array>
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +23,11 @@ struct sc_stencil {
   int64_t den = 1;
   std::vector<std::array<int32_t, 3>> off;
   std::vector<int64_t> num;
+  // kernel-ready weights for the last grid spacing used (host cache, guarded
+  // by `mu`; a stencil handle may be shared between threads)
+  mutable std::mutex mu;
+  mutable double cached_h = -1.0;
+  mutable std::shared_ptr<void> cached_ks;
 };
 
 namespace sc {
@@ -148,6 +155,18 @@ sc_status ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_solve
                   sc_solve_stats* stats, hipStream_t st);
 sc_status grid_diagnostics(const sc_grid* u, double h, double eps, double* mass, double* energy,
                            hipStream_t st);
+sc_status server_create(const sc_server_opts* opts, sc_server** out);
+sc_status server_submit(sc_server* s, const sc_request* r, uint64_t* id);
+sc_status server_poll(sc_server* s, sc_result* out, int32_t max, int32_t* n, int32_t wait_ms);
+sc_status server_cancel(sc_server* s, uint64_t id);
+sc_status server_load(sc_server* s, int32_t* queued, int32_t* active, int32_t* fin, uint64_t* bytes);
+void server_destroy(sc_server* s);
+// shared validation / set-up helpers (solver.cpp)
+sc_status check_grid(const sc_grid* g, const char* what);
+void* interior(const sc_grid* g);
+void fill_opts(const sc_solve_opts* in, sc_solve_opts* o);
+sc_status check_ch(const sc_stencil* lap, const sc_ch_params* prm, int dim);
+sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* ksA, KStencil* ksL);
 
 // --------------------------------------------------------- workspace pool
 // Grow-only per-device cache of device allocations (never returned to the

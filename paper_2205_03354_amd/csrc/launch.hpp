@@ -8,15 +8,16 @@
 
 namespace sc {
 
-// Output rows (2D) per tile: aim at ~5600 one-wave tiles (about 22 per CU,
-// more than can be resident, so the tail is short) without making tiles so
+// Output rows (2D) per tile: aim at ~8192 one-wave tiles, about two rounds
+// of the waves one MI355X keeps resident (16 per CU), so that the tiles in
+// flight at any moment cover a compact band of rows, without making tiles so
 // short that the 2R halo rows dominate.
 inline int tile_rows_2d(int64_t n1, int64_t strips, int R) {
   if (const char* e = std::getenv("SCOMP_TY2D")) {
     const int v = std::atoi(e);
     if (v > 0) return v;
   }
-  int64_t ty = (n1 * strips + 5599) / 5600;
+  int64_t ty = (n1 * strips + 8191) / 8192;
   const int64_t lo = 4 * R > 12 ? 4 * R : 12;
   if (ty < lo) ty = lo;
   if (ty > n1) ty = n1;

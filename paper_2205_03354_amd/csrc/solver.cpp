@@ -10,7 +10,7 @@
 #include <map>
 #include <mutex>
 
-#include "internal.hpp"
+#include "task.hpp"
 
 namespace sc {
 
@@ -58,81 +58,6 @@ namespace {
 
 size_t esize(int dtype) { return dtype == SC_F64 ? 8 : 4; }
 
-// A zeroed workspace vector: `base` addresses the interior (0,0,0) element,
-// which is 256-byte aligned, as is every row.
-struct DevVec {
-  void* alloc = nullptr;
-  void* base = nullptr;
-  Layout lay;
-  int dtype = SC_F64;
-};
-
-// Returns workspace to the pool when a call ends, after the stream has
-// drained (the pool is shared by every stream of the process).
-struct VecGuard {
-  hipStream_t st = nullptr;
-  std::vector<void*> raw;
-  ~VecGuard() {
-    if (!raw.empty()) (void)hipStreamSynchronize(st);
-    for (auto* r : raw) pool_free(r);
-  }
-};
-
-sc_status make_vec(int dim, const int64_t* n, int halo, int dtype, hipStream_t st, DevVec* v,
-                   VecGuard* guard) {
-  const int64_t es = (int64_t)esize(dtype);
-  const int64_t align_e = 256 / es;
-  const int64_t pitch = (n[0] + 2 * halo + align_e - 1) / align_e * align_e;
-  const int64_t rows = n[1] + 2 * halo;
-  const int64_t zp = pitch * rows;
-  const int64_t planes = dim == 3 ? n[2] + 2 * halo : 1;
-  const size_t bytes = (size_t)(zp * planes * es) + 256;
-  void* p = pool_alloc(bytes);
-  if (!p) {
-    set_error("device workspace allocation of %zu bytes failed", bytes);
-    return SC_ENOMEM;
-  }
-  guard->raw.push_back(p);
-  v->alloc = p;
-  v->dtype = dtype;
-  v->lay.pitch = pitch;
-  v->lay.zpitch = zp;
-  v->lay.halo = halo;
-  const int64_t pad = (256 - (halo * es) % 256) % 256;
-  const int64_t off_e = (dim == 3 ? halo * zp : 0) + halo * pitch + halo;
-  v->base = static_cast<char*>(p) + pad + off_e * es;
-  SC_HIP_CHECK(hipMemsetAsync(p, 0, bytes, st));
-  return SC_OK;
-}
-
-// Scalars: one device block per solve level plus a pinned host mirror.
-struct Ctx {
-  hipStream_t st = nullptr;
-  DevScalars* d64 = nullptr;
-  DevScalars* d32 = nullptr;
-  DevScalars* h64 = nullptr;
-  DevScalars* h32 = nullptr;
-  double* partials = nullptr;
-};
-
-DevScalars* pinned_scalars() {
-  thread_local DevScalars* p = nullptr;
-  if (!p) {
-    if (hipHostMalloc((void**)&p, 2 * sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-    }
-  }
-  return p;
-}
-
-sc_status read_scalars(Ctx& c, bool both) {
-  SC_HIP_CHECK(hipMemcpyAsync(c.h64, c.d64, sizeof(DevScalars), hipMemcpyDeviceToHost, c.st));
-  if (both) SC_HIP_CHECK(hipMemcpyAsync(c.h32, c.d32, sizeof(DevScalars), hipMemcpyDeviceToHost, c.st));
-  SC_HIP_CHECK(hipStreamSynchronize(c.st));
-  return SC_OK;
-}
-
 SweepLaunch sweep_on(int kind, const KStencil& ks, bool periodic, int dtype, const int64_t* n) {
   SweepLaunch L;
   L.kind = kind;
@@ -143,32 +68,6 @@ SweepLaunch sweep_on(int kind, const KStencil& ks, bool periodic, int dtype, con
   L.n[1] = n[1];
   L.n[2] = n[2];
   return L;
-}
-
-void set_in(SweepLaunch& L, const DevVec& v) {
-  L.in = v.base;
-  L.pin = v.lay.pitch;
-  L.zin = v.lay.zpitch;
-}
-void set_in2(SweepLaunch& L, const DevVec& v) {
-  L.in2 = v.base;
-  L.pin2 = v.lay.pitch;
-  L.zin2 = v.lay.zpitch;
-}
-void set_aux(SweepLaunch& L, const DevVec& v) {
-  L.aux = v.base;
-  L.paux = v.lay.pitch;
-  L.zaux = v.lay.zpitch;
-}
-void set_out(SweepLaunch& L, const DevVec& v) {
-  L.out = v.base;
-  L.pout = v.lay.pitch;
-  L.zout = v.lay.zpitch;
-}
-void set_out2(SweepLaunch& L, const DevVec& v) {
-  L.out2 = v.base;
-  L.pout2 = v.lay.pitch;
-  L.zout2 = v.lay.zpitch;
 }
 
 bool aligned16(const void* p, int64_t pitch, int64_t zpitch, int64_t es, bool three_d) {
@@ -192,160 +91,391 @@ sc_status launch(SweepLaunch L, hipStream_t st) {
   return SC_OK;
 }
 
-// CG iterations until the recurrence converges (done = 1), breaks down
-// (done = 2) or `cap` iterations have been performed. Requires the scalars
-// to hold a fresh (re)start (rr, beta = 0, done = 0) and r = b - A x.
-sc_status cg_iterate(const KStencil& ks, bool periodic, int dtype, const int64_t* n, DevVec& x, DevVec& r,
-                     DevVec* p, int& cur, DevVec& q, DevScalars* d, DevScalars* h, Ctx& c, int64_t cap,
-                     int check_every) {
-  const int64_t start = h->iter;
-  while (true) {
-    const int64_t left = cap - (h->iter - start);
-    if (left <= 0) return SC_OK;
-    const int64_t k_run = std::min<int64_t>(check_every, left);
-    for (int64_t k = 0; k < k_run; ++k) {
-      SweepLaunch L = sweep_on(K_CGDIR, ks, periodic, dtype, n);
-      set_in(L, r);
-      set_in2(L, p[cur]);
-      set_out(L, p[1 - cur]);
-      set_out2(L, q);
-      L.scal = d;
-      L.partials = c.partials;
-      sc_status s = launch(L, c.st);
-      if (s != SC_OK) return s;
-      SC_HIP_CHECK(launch_cg_update(dtype, x.base, r.base, p[1 - cur].base, q.base, x.lay, n, d,
-                                    c.partials, c.st));
-      cur = 1 - cur;
-    }
-    SC_HIP_CHECK(hipMemcpyAsync(h, d, sizeof(DevScalars), hipMemcpyDeviceToHost, c.st));
-    SC_HIP_CHECK(hipStreamSynchronize(c.st));
-    if (h->done != 0) return SC_OK;
-  }
+
+Layout make_layout(int dim, const int64_t* n, int halo, int dtype) {
+  const int64_t es = (int64_t)esize(dtype);
+  const int64_t align_e = 256 / es;
+  Layout lay;
+  lay.pitch = (n[0] + 2 * halo + align_e - 1) / align_e * align_e;
+  lay.zpitch = lay.pitch * (n[1] + 2 * halo);
+  lay.halo = halo;
+  (void)dim;
+  return lay;
 }
 
-// True residual r = b - A x; flag = 1 also restarts the CG recurrence.
-sc_status residual(const KStencil& ks, bool periodic, const int64_t* n, DevVec& x, DevVec& b, DevVec& r,
-                   DevScalars* d, Ctx& c, int flag) {
-  SweepLaunch L = sweep_on(K_RESID, ks, periodic, SC_F64, n);
-  set_in(L, x);
-  set_aux(L, b);
-  set_out(L, r);
-  L.scal = d;
-  L.partials = c.partials;
+size_t vec_bytes(int dim, const int64_t* n, int halo, int dtype) {
+  const Layout lay = make_layout(dim, n, halo, dtype);
+  const int64_t planes = dim == 3 ? n[2] + 2 * halo : 1;
+  const size_t raw = (size_t)(lay.zpitch * planes) * esize(dtype) + 256;
+  return (raw + 4095) & ~(size_t)4095;
+}
+
+int partial_slots(const TaskSpec& sp) {
+  int slots = kElemBlocks;
+  for (int dt : {SC_F64, SC_F32}) {
+    SweepLaunch L = sweep_on(K_CGDIR, sp.ksA, true, dt, sp.n);
+    slots = std::max(slots, sweep_blocks(L));
+    if (sp.kind == TASK_CH) {
+      SweepLaunch L2 = sweep_on(K_CHRHS, sp.ksL, true, dt, sp.n);
+      slots = std::max(slots, sweep_blocks(L2));
+    }
+  }
+  return slots;
+}
+
+// ------------------------------------------------------- pinned host slots
+std::mutex g_pin_mu;
+std::vector<DevScalars*> g_pin_free;
+
+}  // namespace
+
+DevScalars* pinned_pair_alloc() {
+  std::lock_guard<std::mutex> g(g_pin_mu);
+  if (g_pin_free.empty()) {
+    constexpr int kPairs = 1024;
+    DevScalars* arena = nullptr;
+    if (hipHostMalloc((void**)&arena, sizeof(DevScalars) * 2 * kPairs, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    for (int i = kPairs - 1; i >= 0; --i) g_pin_free.push_back(arena + 2 * i);
+  }
+  DevScalars* p = g_pin_free.back();
+  g_pin_free.pop_back();
+  std::memset(p, 0, 2 * sizeof(DevScalars));
+  return p;
+}
+
+void pinned_pair_free(DevScalars* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(g_pin_mu);
+  g_pin_free.push_back(p);
+}
+
+size_t task_footprint(const TaskSpec& sp) {
+  const int halo = sp.kind == TASK_BVP ? sp.ksA.R : 0;
+  const bool f32 = sp.o.precision == SC_PREC_F32_IR;
+  size_t b = 0;
+  const size_t v64 = vec_bytes(sp.dim, sp.n, halo, SC_F64);
+  const size_t v32 = vec_bytes(sp.dim, sp.n, halo, SC_F32);
+  if (f32)
+    b = 3 * v64 + 5 * v32;  // x b r64 | r d p0 p1 q
+  else
+    b = 6 * v64;            // x b r p0 p1 q
+  b += 4096 + (size_t)partial_slots(sp) * 3 * sizeof(double);
+  return b;
+}
+
+// ------------------------------------------------------------------ task
+SolveTask::~SolveTask() {
+  if (st_ && !allocs_.empty()) (void)hipStreamSynchronize(st_);
+  for (auto& g : graph_)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (void* p : allocs_) pool_free(p);
+  if (h64_) pinned_pair_free(h64_);
+}
+
+sc_status SolveTask::make(Vec* v, int dtype) {
+  const size_t bytes = vec_bytes(spec_.dim, spec_.n, halo_, dtype);
+  void* p = pool_alloc(bytes);
+  if (!p) {
+    set_error("device workspace allocation of %zu bytes failed", bytes);
+    return SC_ENOMEM;
+  }
+  allocs_.push_back(p);
+  bytes_ += bytes;
+  v->alloc = p;
+  v->lay = make_layout(spec_.dim, spec_.n, halo_, dtype);
+  const int64_t es = (int64_t)esize(dtype);
+  const int64_t pad = (256 - (halo_ * es) % 256) % 256;
+  const int64_t off_e = (spec_.dim == 3 ? halo_ * v->lay.zpitch : 0) + halo_ * v->lay.pitch + halo_;
+  v->base = static_cast<char*>(p) + pad + off_e * es;
+  SC_HIP_CHECK(hipMemsetAsync(p, 0, bytes, st_));
+  return SC_OK;
+}
+
+sc_status SolveTask::init(const TaskSpec& spec, hipStream_t st) {
+  spec_ = spec;
+  st_ = st;
+  periodic_ = spec.kind == TASK_CH;
+  f32_ = spec.o.precision == SC_PREC_F32_IR;
+  halo_ = periodic_ ? 0 : spec.ksA.R;
+  h64_ = pinned_pair_alloc();
+  if (!h64_) {
+    set_error("pinned host allocation failed");
+    return SC_ENOMEM;
+  }
+  h32_ = h64_ + 1;
+  const size_t slots = (size_t)partial_slots(spec_);
+  const size_t blk = 2 * sizeof(DevScalars) + 256 + slots * 3 * sizeof(double);
+  dev_block_ = pool_alloc(blk);
+  if (!dev_block_) {
+    set_error("device allocation failed");
+    return SC_ENOMEM;
+  }
+  allocs_.push_back(dev_block_);
+  bytes_ += (blk + 4095) & ~(size_t)4095;
+  SC_HIP_CHECK(hipMemsetAsync(dev_block_, 0, 2 * sizeof(DevScalars), st_));
+  d64_ = static_cast<DevScalars*>(dev_block_);
+  d32s_ = d64_ + 1;
+  partials_ = reinterpret_cast<double*>(static_cast<char*>(dev_block_) + 2 * sizeof(DevScalars) + 256);
+  sc_status s;
+  if ((s = make(&x_, SC_F64)) != SC_OK || (s = make(&b_, SC_F64)) != SC_OK || (s = make(&r64_, SC_F64)) != SC_OK)
+    return s;
+  const int vt = f32_ ? SC_F32 : SC_F64;
+  if (f32_) {
+    if ((s = make(&r32_, SC_F32)) != SC_OK || (s = make(&d32_, SC_F32)) != SC_OK) return s;
+  }
+  if ((s = make(&p_[0], vt)) != SC_OK || (s = make(&p_[1], vt)) != SC_OK || (s = make(&q_, vt)) != SC_OK) return s;
+  phase_ = P_NONE;
+  return SC_OK;
+}
+
+sc_status SolveTask::sweep(int kind, int dtype, const KStencil& ks, const void* in, const Layout* lin,
+                           const void* in2, const void* aux, void* out, void* out2, const Layout& lout, int flag,
+                           double c0, double c1, double c2, DevScalars* scal, const GridView* in_view,
+                           const GridView* aux_view) {
+  SweepLaunch L = sweep_on(kind, ks, periodic_, dtype, spec_.n);
+  if (in_view) {
+    L.in = in_view->p;
+    L.pin = in_view->pitch;
+    L.zin = in_view->zpitch;
+  } else {
+    L.in = in;
+    L.pin = lin->pitch;
+    L.zin = lin->zpitch;
+  }
+  L.in2 = in2;
+  L.pin2 = lout.pitch;
+  L.zin2 = lout.zpitch;
+  if (aux_view) {
+    L.aux = aux_view->p;
+    L.paux = aux_view->pitch;
+    L.zaux = aux_view->zpitch;
+  } else {
+    L.aux = aux;
+    L.paux = lout.pitch;
+    L.zaux = lout.zpitch;
+  }
+  L.out = out;
+  L.pout = lout.pitch;
+  L.zout = lout.zpitch;
+  L.out2 = out2;
+  L.pout2 = lout.pitch;
+  L.zout2 = lout.zpitch;
+  L.scal = scal;
+  L.partials = partials_;
   L.flag = flag;
-  return launch(L, c.st);
+  L.c0 = c0;
+  L.c1 = c1;
+  L.c2 = c2;
+  return launch(L, st_);
 }
 
-// Plain FP64 CG on A x = b; b's scalars (bb, rr_stop) are set.
-sc_status solve_f64(const KStencil& ks, bool periodic, int dim, const int64_t* n, DevVec& x, DevVec& b,
-                    const sc_solve_opts& o, Ctx& c, VecGuard& g, sc_solve_stats* stats) {
-  DevVec r, p[2], q;
-  sc_status s;
-  if ((s = make_vec(dim, n, x.lay.halo, SC_F64, c.st, &r, &g)) != SC_OK) return s;
-  if ((s = make_vec(dim, n, x.lay.halo, SC_F64, c.st, &p[0], &g)) != SC_OK) return s;
-  if ((s = make_vec(dim, n, x.lay.halo, SC_F64, c.st, &p[1], &g)) != SC_OK) return s;
-  if ((s = make_vec(dim, n, x.lay.halo, SC_F64, c.st, &q, &g)) != SC_OK) return s;
-  int cur = 0;
-  int outer = 0;
-  int stalled = 0;
-  double best = HUGE_VAL;
-  sc_status result = SC_OK;
-  while (true) {
-    if ((s = residual(ks, periodic, n, x, b, r, c.d64, c, 1)) != SC_OK) return s;
-    ++outer;
-    if ((s = read_scalars(c, false)) != SC_OK) return s;
-    if (c.h64->rr_true <= c.h64->rr_stop) break;
-    if (c.h64->iter >= o.max_iter) {
-      result = SC_ENOTCONV;
-      set_error("CG did not reach the tolerance in %lld iterations", (long long)o.max_iter);
-      break;
-    }
-    // restarts that no longer halve the true residual: the tolerance is
-    // below the rounding floor of the operator
-    stalled = (c.h64->rr_true > 0.25 * best) ? stalled + 1 : 0;
-    best = std::min(best, c.h64->rr_true);
-    if (stalled >= 3) {
-      result = SC_ENOTCONV;
-      set_error("CG stagnated at relative residual %g (rounding floor above tol)",
-                std::sqrt(c.h64->rr_true / c.h64->bb));
-      break;
-    }
-    s = cg_iterate(ks, periodic, SC_F64, n, x, r, p, cur, q, c.d64, c.h64, c, o.max_iter - c.h64->iter,
-                   o.check_every);
-    if (s != SC_OK) return s;
-    if (c.h64->done == 2) {
-      set_error("CG breakdown: <p, Ap> = %g after %lld iterations", c.h64->pq, (long long)c.h64->iter);
-      result = SC_EBREAKDOWN;
-      if ((s = residual(ks, periodic, n, x, b, r, c.d64, c, 0)) != SC_OK) return s;
-      if ((s = read_scalars(c, false)) != SC_OK) return s;
-      break;
-    }
-  }
-  if (stats) {
-    stats->iterations = c.h64->iter;
-    stats->outer = outer;
-    stats->bnorm = std::sqrt(c.h64->bb);
-    stats->rel_residual = c.h64->bb > 0 ? std::sqrt(c.h64->rr_true / c.h64->bb) : 0.0;
-  }
-  return result;
+// The host copies carry an iteration count of -1 until the copy has landed.
+sc_status SolveTask::enqueue_read(bool both) {
+  h64_->iter = -1;
+  if (both) h32_->iter = -1;
+  SC_HIP_CHECK(hipMemcpyAsync(h64_, d64_, sizeof(DevScalars), hipMemcpyDeviceToHost, st_));
+  if (both) SC_HIP_CHECK(hipMemcpyAsync(h32_, d32s_, sizeof(DevScalars), hipMemcpyDeviceToHost, st_));
+  return SC_OK;
 }
 
-// FP32 CG (FP64 reductions) inside FP64 iterative refinement.
-sc_status solve_ir(const KStencil& ks, bool periodic, int dim, const int64_t* n, DevVec& x, DevVec& b,
-                   const sc_solve_opts& o, Ctx& c, VecGuard& g, sc_solve_stats* stats) {
-  DevVec r64, r32, d32, p[2], q;
-  sc_status s;
-  const int halo = x.lay.halo;
-  if ((s = make_vec(dim, n, halo, SC_F64, c.st, &r64, &g)) != SC_OK) return s;
-  if ((s = make_vec(dim, n, halo, SC_F32, c.st, &r32, &g)) != SC_OK) return s;
-  if ((s = make_vec(dim, n, halo, SC_F32, c.st, &d32, &g)) != SC_OK) return s;
-  if ((s = make_vec(dim, n, halo, SC_F32, c.st, &p[0], &g)) != SC_OK) return s;
-  if ((s = make_vec(dim, n, halo, SC_F32, c.st, &p[1], &g)) != SC_OK) return s;
-  if ((s = make_vec(dim, n, halo, SC_F32, c.st, &q, &g)) != SC_OK) return s;
-  int cur = 0;
-  int outer = 0;
-  int stalled = 0;
-  double best = HUGE_VAL;
-  sc_status result = SC_OK;
-  const double inner2 = o.inner_tol * o.inner_tol;
-  while (true) {
-    if ((s = residual(ks, periodic, n, x, b, r64, c.d64, c, 0)) != SC_OK) return s;
-    ++outer;
-    if ((s = read_scalars(c, true)) != SC_OK) return s;
-    if (c.h64->rr_true <= c.h64->rr_stop) break;
-    if (c.h32->iter >= o.max_iter) {
-      result = SC_ENOTCONV;
-      set_error("refinement did not reach the tolerance in %lld inner iterations", (long long)o.max_iter);
-      break;
-    }
-    stalled = (c.h64->rr_true > 0.25 * best) ? stalled + 1 : 0;
-    best = std::min(best, c.h64->rr_true);
-    if (stalled >= 3) {
-      result = SC_ENOTCONV;
-      set_error("refinement stagnated at relative residual %g", std::sqrt(c.h64->rr_true / c.h64->bb));
-      break;
-    }
-    SC_HIP_CHECK(launch_ir_prepare((const double*)r64.base, r64.lay, (float*)r32.base, (float*)d32.base,
-                                   r32.lay, n, c.d64, c.d32, inner2, c.partials, c.st));
-    const int64_t before = c.h32->iter;
-    s = cg_iterate(ks, periodic, SC_F32, n, d32, r32, p, cur, q, c.d32, c.h32, c, o.max_iter - c.h32->iter,
-                   o.check_every);
-    if (s != SC_OK) return s;
-    if (c.h32->done == 2 && c.h32->iter == before) {
-      set_error("FP32 CG breakdown at the first inner iteration (<p, Ap> = %g)", c.h32->pq);
-      result = SC_EBREAKDOWN;
-      break;
-    }
-    SC_HIP_CHECK(launch_ir_update((double*)x.base, x.lay, (const float*)d32.base, d32.lay, n, c.d64, c.st));
-  }
-  if (stats) {
-    stats->iterations = c.h32->iter;
-    stats->outer = outer;
-    stats->bnorm = std::sqrt(c.h64->bb);
-    stats->rel_residual = c.h64->bb > 0 ? std::sqrt(c.h64->rr_true / c.h64->bb) : 0.0;
-  }
-  return result;
+sc_status SolveTask::enqueue_residual(int flag) {
+  return sweep(K_RESID, SC_F64, spec_.ksA, x_.base, &x_.lay, nullptr, b_.base, r64_.base, nullptr, x_.lay, flag, 0,
+               0, 0, d64_);
 }
+
+// K CG iterations (direction sweep + update each), replayed from a graph
+// captured on first use when K is even and the ping-pong parity matches.
+sc_status SolveTask::enqueue_block(bool f32) {
+  const int dtype = f32 ? SC_F32 : SC_F64;
+  DevScalars* ds = f32 ? d32s_ : d64_;
+  const DevScalars* hs = f32 ? h32_ : h64_;
+  Vec& x = f32 ? d32_ : x_;
+  Vec& r = f32 ? r32_ : r64_;
+  const int gi = f32 ? 1 : 0;
+  const int K = std::max(1, spec_.o.check_every);
+  const int64_t left = spec_.o.max_iter - hs->iter;
+  auto one = [&]() -> sc_status {
+    sc_status s = sweep(K_CGDIR, dtype, spec_.ksA, r.base, &r.lay, p_[cur_].base, nullptr, p_[1 - cur_].base,
+                        q_.base, r.lay, 0, 0, 0, 0, ds);
+    if (s != SC_OK) return s;
+    SC_HIP_CHECK(launch_cg_update(dtype, x.base, r.base, p_[1 - cur_].base, q_.base, x.lay, spec_.n, ds, partials_,
+                                  st_));
+    cur_ = 1 - cur_;
+    return SC_OK;
+  };
+  const bool graph_ok = spec_.o.use_graph && K % 2 == 0 && left >= K && cur_ == 0;
+  if (graph_ok) {
+    if (!graph_[gi]) {
+      hipGraph_t g = nullptr;
+      SC_HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+      sc_status s = SC_OK;
+      for (int k = 0; k < K && s == SC_OK; ++k) s = one();
+      hipGraph_t captured = nullptr;
+      const hipError_t e = hipStreamEndCapture(st_, &captured);
+      if (s != SC_OK) {
+        if (captured) (void)hipGraphDestroy(captured);
+        return s;
+      }
+      if (e != hipSuccess) {
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        return SC_EDEVICE;
+      }
+      g = captured;
+      const hipError_t ei = hipGraphInstantiate(&graph_[gi], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        graph_[gi] = nullptr;
+        set_error("graph instantiation failed: %s", hipGetErrorString(ei));
+        return SC_EDEVICE;
+      }
+      graph_k_[gi] = K;
+    }
+    SC_HIP_CHECK(hipGraphLaunch(graph_[gi], st_));
+  } else {
+    const int64_t k_run = std::min<int64_t>(K, left);
+    for (int64_t k = 0; k < k_run; ++k) {
+      sc_status s = one();
+      if (s != SC_OK) return s;
+    }
+  }
+  return enqueue_read(f32);
+}
+
+sc_status SolveTask::start(const GridView& u0, const GridView& f, const GridView* g) {
+  SC_HIP_CHECK(launch_copy(u0.p, u0.pitch, u0.zpitch, (double*)x_.base, x_.lay.pitch, x_.lay.zpitch, spec_.n, st_));
+  const double tol2 = spec_.o.tol * spec_.o.tol;
+  sc_status s;
+  if (spec_.kind == TASK_BVP) {
+    // b = f - A g_ring (the zero ring of q when g is absent)
+    GridView zero{(const double*)q_.base, q_.lay.pitch, q_.lay.zpitch};
+    if (f32_) zero = GridView{(const double*)r64_.base, r64_.lay.pitch, r64_.lay.zpitch};
+    const GridView& gv = g ? *g : zero;
+    s = sweep(K_BVPRHS, SC_F64, spec_.ksA, nullptr, nullptr, nullptr, nullptr, b_.base, nullptr, b_.lay, 0, 0, 0,
+              tol2, d64_, &gv, &f);
+  } else {
+    // rhs = u + dt L(u^3 - (1+S) u), from x0 = u
+    s = sweep(K_CHRHS, SC_F64, spec_.ksL, x_.base, &x_.lay, nullptr, nullptr, b_.base, nullptr, b_.lay, 0,
+              spec_.dt, 1.0 + spec_.S, tol2, d64_);
+  }
+  if (s != SC_OK) return s;
+  outer_ = 1;
+  stalled_ = 0;
+  best_ = HUGE_VAL;
+  if (!f32_) {
+    if ((s = enqueue_residual(1)) != SC_OK) return s;
+    phase_ = P_CHECK64;
+    return enqueue_read(false);
+  }
+  if ((s = enqueue_residual(0)) != SC_OK) return s;
+  phase_ = P_OUTER;
+  return enqueue_read(true);
+}
+
+void SolveTask::finish(sc_status s) {
+  status_ = s;
+  phase_ = P_DONE;
+  stats_.iterations = f32_ ? h32_->iter : h64_->iter;
+  stats_.outer = outer_;
+  stats_.bnorm = std::sqrt(h64_->bb);
+  stats_.rel_residual = h64_->bb > 0 ? std::sqrt(h64_->rr_true / h64_->bb) : 0.0;
+}
+
+sc_status SolveTask::advance(bool* done) {
+  *done = false;
+  if (__atomic_load_n(&h64_->iter, __ATOMIC_ACQUIRE) < 0 || __atomic_load_n(&h32_->iter, __ATOMIC_ACQUIRE) < 0)
+    return SC_OK;  // the last host copy has not landed yet: call again later
+  const sc_solve_opts& o = spec_.o;
+  sc_status s;
+  auto stagnated = [&]() {
+    stalled_ = (h64_->rr_true > 0.25 * best_) ? stalled_ + 1 : 0;
+    best_ = std::min(best_, h64_->rr_true);
+    return stalled_ >= 3;
+  };
+  switch (phase_) {
+    case P_CHECK64:
+      if (h64_->rr_true <= h64_->rr_stop) {
+        finish(SC_OK);
+      } else if (h64_->iter >= o.max_iter) {
+        set_error("CG did not reach the tolerance in %lld iterations", (long long)o.max_iter);
+        finish(SC_ENOTCONV);
+      } else if (stagnated()) {
+        set_error("CG stagnated at relative residual %g (rounding floor above tol)",
+                  std::sqrt(h64_->rr_true / h64_->bb));
+        finish(SC_ENOTCONV);
+      } else {
+        if ((s = enqueue_block(false)) != SC_OK) return s;
+        phase_ = P_ITER64;
+      }
+      break;
+    case P_ITER64:
+      if (h64_->done == 2) {
+        set_error("CG breakdown: <p, Ap> = %g after %lld iterations", h64_->pq, (long long)h64_->iter);
+        pending_ = SC_EBREAKDOWN;
+        if ((s = enqueue_residual(0)) != SC_OK || (s = enqueue_read(false)) != SC_OK) return s;
+        phase_ = P_FINAL;
+      } else if (h64_->done == 1) {
+        if ((s = enqueue_residual(1)) != SC_OK || (s = enqueue_read(false)) != SC_OK) return s;
+        ++outer_;
+        phase_ = P_CHECK64;
+      } else if (h64_->iter >= o.max_iter) {
+        set_error("CG did not reach the tolerance in %lld iterations", (long long)o.max_iter);
+        pending_ = SC_ENOTCONV;
+        if ((s = enqueue_residual(0)) != SC_OK || (s = enqueue_read(false)) != SC_OK) return s;
+        phase_ = P_FINAL;
+      } else {
+        if ((s = enqueue_block(false)) != SC_OK) return s;
+      }
+      break;
+    case P_FINAL:
+      finish(pending_);
+      break;
+    case P_OUTER:
+      if (h64_->rr_true <= h64_->rr_stop) {
+        finish(SC_OK);
+      } else if (h32_->iter >= o.max_iter) {
+        set_error("refinement did not reach the tolerance in %lld inner iterations", (long long)o.max_iter);
+        finish(SC_ENOTCONV);
+      } else if (stagnated()) {
+        set_error("refinement stagnated at relative residual %g", std::sqrt(h64_->rr_true / h64_->bb));
+        finish(SC_ENOTCONV);
+      } else {
+        SC_HIP_CHECK(launch_ir_prepare((const double*)r64_.base, r64_.lay, (float*)r32_.base, (float*)d32_.base,
+                                       r32_.lay, spec_.n, d64_, d32s_, o.inner_tol * o.inner_tol, partials_, st_));
+        inner_start_ = h32_->iter;
+        if ((s = enqueue_block(true)) != SC_OK) return s;
+        phase_ = P_INNER;
+      }
+      break;
+    case P_INNER:
+      if (h32_->done == 2 && h32_->iter == inner_start_) {
+        set_error("FP32 CG breakdown at the first inner iteration (<p, Ap> = %g)", h32_->pq);
+        finish(SC_EBREAKDOWN);
+      } else if (h32_->done != 0 || h32_->iter >= o.max_iter) {
+        SC_HIP_CHECK(launch_ir_update((double*)x_.base, x_.lay, (const float*)d32_.base, d32_.lay, spec_.n, d64_, st_));
+        if ((s = enqueue_residual(0)) != SC_OK || (s = enqueue_read(true)) != SC_OK) return s;
+        ++outer_;
+        phase_ = P_OUTER;
+      } else {
+        if ((s = enqueue_block(true)) != SC_OK) return s;
+      }
+      break;
+    default:
+      break;
+  }
+  *done = phase_ == P_DONE;
+  return SC_OK;
+}
+
+sc_status SolveTask::enqueue_copy_out(double* dst, int64_t pitch, int64_t zpitch) {
+  SC_HIP_CHECK(launch_copy((const double*)x_.base, x_.lay.pitch, x_.lay.zpitch, dst, pitch, zpitch, spec_.n, st_));
+  return SC_OK;
+}
+
+// ---------------------------------------------------------- validation
+namespace {
 
 int64_t grid_bytes(const sc_grid* g) {
   const int64_t h = g->halo;
@@ -357,7 +487,6 @@ int64_t grid_bytes(const sc_grid* g) {
 
 }  // namespace
 
-// Validation shared by the entry points.
 sc_status check_grid(const sc_grid* g, const char* what) {
   if (!g || !g->data) {
     set_error("%s: NULL grid or data", what);
@@ -389,6 +518,10 @@ void* interior(const sc_grid* g) {
   const int64_t es = (int64_t)esize(g->dtype);
   const int64_t off = (g->dim == 3 ? h * g->pitch[1] : 0) + h * g->pitch[0] + h;
   return static_cast<char*>(g->data) + off * es;
+}
+
+static GridView view_of(const sc_grid* g) {
+  return GridView{static_cast<const double*>(interior(g)), g->pitch[0], g->pitch[1]};
 }
 
 bool overlaps(const sc_grid* a, const sc_grid* b) {
@@ -425,8 +558,20 @@ sc_status apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_gr
     set_error("in and out overlap in memory");
     return SC_EINVAL;
   }
-  KStencil ks;
-  if ((r = make_kstencil(s, h, &ks)) != SC_OK) return r;
+  std::shared_ptr<void> cached;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->cached_h == h && s->cached_ks) cached = s->cached_ks;
+  }
+  if (!cached) {
+    auto fresh = std::make_shared<KStencil>();
+    if ((r = make_kstencil(s, h, fresh.get())) != SC_OK) return r;
+    cached = fresh;
+    std::lock_guard<std::mutex> g(s->mu);
+    s->cached_h = h;
+    s->cached_ks = cached;
+  }
+  const KStencil& ks = *static_cast<const KStencil*>(cached.get());
   const int rad = sc_stencil_radius(s);
   if (bc == SC_BC_HALO && in->halo < rad) {
     set_error("halo mode needs in->halo >= radius (%d < %d)", in->halo, rad);
@@ -442,47 +587,6 @@ sc_status apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_gr
   return launch(L, st);
 }
 
-namespace {
-
-sc_status init_ctx(Ctx& c, hipStream_t st, const KStencil& ks, const int64_t* n, VecGuard& g,
-                   const KStencil* ks2 = nullptr) {
-  c.st = st;
-  DevScalars* h = pinned_scalars();
-  if (!h) {
-    set_error("pinned host allocation failed");
-    return SC_ENOMEM;
-  }
-  c.h64 = h;
-  c.h32 = h + 1;
-  void* d = pool_alloc(2 * sizeof(DevScalars));
-  if (!d) {
-    set_error("device allocation failed");
-    return SC_ENOMEM;
-  }
-  g.raw.push_back(d);
-  c.d64 = static_cast<DevScalars*>(d);
-  c.d32 = c.d64 + 1;
-  SC_HIP_CHECK(hipMemsetAsync(d, 0, 2 * sizeof(DevScalars), st));
-  std::memset(c.h64, 0, 2 * sizeof(DevScalars));
-  int slots = kElemBlocks;
-  for (int dt : {SC_F64, SC_F32}) {
-    SweepLaunch L = sweep_on(K_CGDIR, ks, true, dt, n);
-    slots = std::max(slots, sweep_blocks(L));
-    if (ks2) {
-      SweepLaunch L2 = sweep_on(K_CGDIR, *ks2, true, dt, n);
-      slots = std::max(slots, sweep_blocks(L2));
-    }
-  }
-  void* p = pool_alloc((size_t)slots * 3 * sizeof(double));
-  if (!p) {
-    set_error("device allocation failed");
-    return SC_ENOMEM;
-  }
-  g.raw.push_back(p);
-  c.partials = static_cast<double*>(p);
-  return SC_OK;
-}
-
 void fill_opts(const sc_solve_opts* in, sc_solve_opts* o) {
   sc_solve_opts_default(o);
   if (in) *o = *in;
@@ -492,7 +596,82 @@ void fill_opts(const sc_solve_opts* in, sc_solve_opts* o) {
   if (o->check_every <= 0) o->check_every = 64;
 }
 
-}  // namespace
+// The operator of one Cahn-Hilliard step, I + dt eps^2 L o L - dt S L,
+// composed exactly and combined once in extended precision.
+sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* ksA, KStencil* ksL) {
+  sc_status r;
+  sc_stencil* LL = nullptr;
+  if ((r = compose(lap, lap, &LL)) != SC_OK) return r;
+  std::map<std::array<int32_t, 3>, long double> wa;
+  const long double h = prm->h;
+  const long double cLL = (long double)prm->dt * prm->eps * prm->eps / (h * h * h * h);
+  const long double cL = -(long double)prm->dt * prm->S / (h * h);
+  wa[{0, 0, 0}] += 1.0L;
+  for (size_t t = 0; t < LL->num.size(); ++t) wa[LL->off[t]] += cLL * (long double)LL->num[t] / LL->den;
+  for (size_t t = 0; t < lap->num.size(); ++t) wa[lap->off[t]] += cL * (long double)lap->num[t] / lap->den;
+  delete LL;
+  std::vector<std::array<int32_t, 3>> offs;
+  std::vector<long double> ws;
+  for (auto& kv : wa) {
+    offs.push_back(kv.first);
+    ws.push_back(kv.second);
+  }
+  if ((r = make_kstencil(lap->dim, offs, ws, ksA)) != SC_OK) return r;
+  return make_kstencil(lap, prm->h, ksL);
+}
+
+sc_status check_ch(const sc_stencil* lap, const sc_ch_params* prm, int dim) {
+  if (!lap || !prm) {
+    set_error("NULL Laplacian or parameters");
+    return SC_EINVAL;
+  }
+  if (lap->dim != dim || lap->hpow != 2) {
+    set_error("lap must be a %dD second-derivative stencil (hpow 2)", dim);
+    return SC_EINVAL;
+  }
+  if (!(prm->h > 0) || !(prm->dt > 0) || !(prm->eps >= 0) || !std::isfinite(prm->S)) {
+    set_error("invalid Cahn-Hilliard parameters");
+    return SC_EINVAL;
+  }
+  return SC_OK;
+}
+
+// Drive a task to completion on its stream.
+// The blocking entry points run on the caller's stream. The legacy null
+// stream cannot be captured into a graph, so a call made on it runs on a
+// per-thread, per-device non-blocking stream that first waits for the work
+// already queued on the null stream; the call returns only after that stream
+// has drained, so later null-stream work is ordered after it.
+static sc_status blocking_stream(hipStream_t caller, hipStream_t* out) {
+  *out = caller;
+  if (caller) return SC_OK;
+  struct Cached {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+  };
+  thread_local std::map<int, Cached> cache;
+  int dev = 0;
+  SC_HIP_CHECK(hipGetDevice(&dev));
+  Cached& c = cache[dev];
+  if (!c.st) {
+    SC_HIP_CHECK(hipStreamCreateWithFlags(&c.st, hipStreamNonBlocking));
+    SC_HIP_CHECK(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+  }
+  SC_HIP_CHECK(hipEventRecord(c.ev, nullptr));
+  SC_HIP_CHECK(hipStreamWaitEvent(c.st, c.ev, 0));
+  *out = c.st;
+  return SC_OK;
+}
+
+static sc_status run_blocking(SolveTask& t) {
+  bool done = false;
+  while (!done) {
+    SC_HIP_CHECK(hipStreamSynchronize(t.stream()));
+    sc_status s = t.advance(&done);
+    if (s != SC_OK) return s;
+  }
+  return t.status();
+}
 
 sc_status solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, const sc_grid* gr,
                            const sc_solve_opts* opts, sc_grid* u, sc_solve_stats* stats, hipStream_t st) {
@@ -516,57 +695,35 @@ sc_status solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, con
     set_error("operator is %dD but the grid is %dD", op->dim, u->dim);
     return SC_EINVAL;
   }
-  sc_solve_opts o;
-  fill_opts(opts, &o);
-  if (o.precision != SC_PREC_F64 && o.precision != SC_PREC_F32_IR) {
-    set_error("unknown precision %d", o.precision);
+  TaskSpec sp;
+  fill_opts(opts, &sp.o);
+  if (sp.o.precision != SC_PREC_F64 && sp.o.precision != SC_PREC_F32_IR) {
+    set_error("unknown precision %d", sp.o.precision);
     return SC_EINVAL;
   }
-  KStencil ks;
-  if ((r = make_kstencil(op, h, &ks)) != SC_OK) return r;
+  if ((r = make_kstencil(op, h, &sp.ksA)) != SC_OK) return r;
   const int rad = sc_stencil_radius(op);
   if (gr && gr->halo < rad) {
     set_error("g must carry a ring of width >= radius (%d < %d)", gr->halo, rad);
     return SC_EINVAL;
   }
-  const int64_t* n = u->n;
-  const int dim = u->dim;
-  VecGuard g;
-  g.st = st;
-  Ctx c;
-  if ((r = init_ctx(c, st, ks, n, g)) != SC_OK) return r;
-  DevVec x, b, zero;
-  if ((r = make_vec(dim, n, ks.R, SC_F64, st, &x, &g)) != SC_OK) return r;
-  if ((r = make_vec(dim, n, ks.R, SC_F64, st, &b, &g)) != SC_OK) return r;
-  SC_HIP_CHECK(launch_copy((const double*)interior(u), u->pitch[0], u->pitch[1], (double*)x.base,
-                           x.lay.pitch, x.lay.zpitch, n, st));
-  // b = f - A g_ring
-  SweepLaunch L = sweep_on(K_BVPRHS, ks, false, SC_F64, n);
-  if (gr) {
-    L.in = interior(gr);
-    L.pin = gr->pitch[0];
-    L.zin = gr->pitch[1];
-  } else {
-    if ((r = make_vec(dim, n, ks.R, SC_F64, st, &zero, &g)) != SC_OK) return r;
-    set_in(L, zero);
-  }
-  L.aux = interior(f);
-  L.paux = f->pitch[0];
-  L.zaux = f->pitch[1];
-  set_out(L, b);
-  L.scal = c.d64;
-  L.partials = c.partials;
-  L.c2 = o.tol * o.tol;
-  if ((r = launch(L, st)) != SC_OK) return r;
-  sc_status res = o.precision == SC_PREC_F64 ? solve_f64(ks, false, dim, n, x, b, o, c, g, stats)
-                                             : solve_ir(ks, false, dim, n, x, b, o, c, g, stats);
+  if ((r = blocking_stream(st, &st)) != SC_OK) return r;
+  sp.kind = TASK_BVP;
+  sp.dim = u->dim;
+  for (int a = 0; a < 3; ++a) sp.n[a] = u->n[a];
+  SolveTask t;
+  if ((r = t.init(sp, st)) != SC_OK) return r;
+  const GridView gv = gr ? view_of(gr) : GridView{};
+  if ((r = t.start(view_of(u), view_of(f), gr ? &gv : nullptr)) != SC_OK) return r;
+  const sc_status res = run_blocking(t);
   if (res == SC_OK || res == SC_ENOTCONV || res == SC_EBREAKDOWN) {
-    SC_HIP_CHECK(launch_copy((const double*)x.base, x.lay.pitch, x.lay.zpitch, (double*)interior(u), u->pitch[0],
-                             u->pitch[1], n, st));
+    if ((r = t.enqueue_copy_out(static_cast<double*>(interior(u)), u->pitch[0], u->pitch[1])) != SC_OK) return r;
     SC_HIP_CHECK(hipStreamSynchronize(st));
   }
-  if (stats)
+  if (stats) {
+    *stats = t.stats();
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
   return res;
 }
 
@@ -574,78 +731,33 @@ sc_status ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_solve
                   sc_solve_stats* stats, hipStream_t st) {
   const auto t0 = std::chrono::steady_clock::now();
   sc_status r;
-  if (!lap || !prm) {
-    set_error("NULL Laplacian or parameters");
-    return SC_EINVAL;
-  }
   if ((r = check_grid(u, "u")) != SC_OK) return r;
   if (u->dtype != SC_F64) {
     set_error("u must be FP64");
     return SC_EINVAL;
   }
-  if (lap->dim != u->dim || lap->hpow != 2) {
-    set_error("lap must be a %dD second-derivative stencil (hpow 2)", u->dim);
-    return SC_EINVAL;
-  }
-  if (!(prm->h > 0) || !(prm->dt > 0) || !(prm->eps >= 0) || !std::isfinite(prm->S)) {
-    set_error("invalid Cahn-Hilliard parameters");
-    return SC_EINVAL;
-  }
-  sc_solve_opts o;
-  fill_opts(opts, &o);
-  const int dim = u->dim;
-  const int64_t* n = u->n;
-  // A = I + dt eps^2 L o L - dt S L, composed exactly, combined once in
-  // extended precision.
-  sc_stencil* LL = nullptr;
-  if ((r = compose(lap, lap, &LL)) != SC_OK) return r;
-  std::map<std::array<int32_t, 3>, long double> wa;
-  const long double h = prm->h;
-  const long double cLL = (long double)prm->dt * prm->eps * prm->eps / (h * h * h * h);
-  const long double cL = -(long double)prm->dt * prm->S / (h * h);
-  wa[{0, 0, 0}] += 1.0L;
-  for (size_t t = 0; t < LL->num.size(); ++t) wa[LL->off[t]] += cLL * (long double)LL->num[t] / LL->den;
-  for (size_t t = 0; t < lap->num.size(); ++t) wa[lap->off[t]] += cL * (long double)lap->num[t] / lap->den;
-  delete LL;
-  std::vector<std::array<int32_t, 3>> offs;
-  std::vector<long double> ws;
-  for (auto& kv : wa) {
-    offs.push_back(kv.first);
-    ws.push_back(kv.second);
-  }
-  KStencil ksA, ksL;
-  if ((r = make_kstencil(dim, offs, ws, &ksA)) != SC_OK) return r;
-  if ((r = make_kstencil(lap, prm->h, &ksL)) != SC_OK) return r;
-  VecGuard g;
-  g.st = st;
-  Ctx c;
-  if ((r = init_ctx(c, st, ksA, n, g, &ksL)) != SC_OK) return r;
-  DevVec x, b;
-  if ((r = make_vec(dim, n, 0, SC_F64, st, &x, &g)) != SC_OK) return r;
-  if ((r = make_vec(dim, n, 0, SC_F64, st, &b, &g)) != SC_OK) return r;
-  SC_HIP_CHECK(launch_copy((const double*)interior(u), u->pitch[0], u->pitch[1], (double*)x.base,
-                           x.lay.pitch, x.lay.zpitch, n, st));
-  // rhs = u + dt L(u^3 - (1+S) u)
-  SweepLaunch L = sweep_on(K_CHRHS, ksL, true, SC_F64, n);
-  L.in = interior(u);
-  L.pin = u->pitch[0];
-  L.zin = u->pitch[1];
-  set_out(L, b);
-  L.scal = c.d64;
-  L.partials = c.partials;
-  L.c0 = prm->dt;
-  L.c1 = 1.0 + prm->S;
-  L.c2 = o.tol * o.tol;
-  if ((r = launch(L, st)) != SC_OK) return r;
-  sc_status res = o.precision == SC_PREC_F64 ? solve_f64(ksA, true, dim, n, x, b, o, c, g, stats)
-                                             : solve_ir(ksA, true, dim, n, x, b, o, c, g, stats);
+  if ((r = check_ch(lap, prm, u->dim)) != SC_OK) return r;
+  TaskSpec sp;
+  fill_opts(opts, &sp.o);
+  if ((r = ch_operator(lap, prm, &sp.ksA, &sp.ksL)) != SC_OK) return r;
+  sp.kind = TASK_CH;
+  sp.dim = u->dim;
+  for (int a = 0; a < 3; ++a) sp.n[a] = u->n[a];
+  sp.dt = prm->dt;
+  sp.S = prm->S;
+  if ((r = blocking_stream(st, &st)) != SC_OK) return r;
+  SolveTask t;
+  if ((r = t.init(sp, st)) != SC_OK) return r;
+  if ((r = t.start(view_of(u), GridView{}, nullptr)) != SC_OK) return r;
+  const sc_status res = run_blocking(t);
   if (res == SC_OK) {
-    SC_HIP_CHECK(launch_copy((const double*)x.base, x.lay.pitch, x.lay.zpitch, (double*)interior(u), u->pitch[0],
-                             u->pitch[1], n, st));
+    if ((r = t.enqueue_copy_out(static_cast<double*>(interior(u)), u->pitch[0], u->pitch[1])) != SC_OK) return r;
   }
   SC_HIP_CHECK(hipStreamSynchronize(st));
-  if (stats)
+  if (stats) {
+    *stats = t.stats();
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
   return res;
 }
 
@@ -657,8 +769,6 @@ sc_status grid_diagnostics(const sc_grid* u, double h, double eps, double* mass,
     set_error("diagnostics need an FP64 grid and h > 0");
     return SC_EINVAL;
   }
-  VecGuard g;
-  g.st = st;
   void* p = pool_alloc(kElemBlocks * 3 * sizeof(double));
   void* t = pool_alloc(256);
   if (!p || !t) {
@@ -667,8 +777,16 @@ sc_status grid_diagnostics(const sc_grid* u, double h, double eps, double* mass,
     set_error("device allocation failed");
     return SC_ENOMEM;
   }
-  g.raw.push_back(p);
-  g.raw.push_back(t);
+  struct Release {
+    hipStream_t st;
+    void* a;
+    void* b;
+    ~Release() {
+      (void)hipStreamSynchronize(st);
+      pool_free(a);
+      pool_free(b);
+    }
+  } rel{st, p, t};
   SC_HIP_CHECK(hipMemsetAsync(t, 0, 256, st));
   double* out3 = reinterpret_cast<double*>(static_cast<char*>(t) + 64);
   SC_HIP_CHECK(launch_diagnostics((const double*)interior(u), u->pitch[0], u->pitch[1], u->dim, u->n,

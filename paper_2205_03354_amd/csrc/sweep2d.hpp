@@ -242,6 +242,10 @@ __global__ void __launch_bounds__(64)
                                        0, 0);
     }
   };
+  // The look-ahead wait counts KSLOW DMA instructions per row, and a DMA
+  // whose lanes are all masked off is skipped by the branch around it, so
+  // lane 0 always issues: when its own column is not needed it re-reads
+  // column 0 of the row into its LDS slot, which no stored output reads.
   auto issue_slow = [&](int q) {
     const int slot = q % NRING;
     const int64_t gy = grid_row(q);
@@ -258,8 +262,9 @@ __global__ void __launch_bounds__(64)
         } else {
           ok = ok && col >= -R;
         }
-        if (ok)
-          __builtin_amdgcn_global_load_lds((const void*)(rp + col * DPE + (d % DPE)),
+        const int64_t off = ok ? col * DPE + (d % DPE) : 0;
+        if (ok || lane == 0)
+          __builtin_amdgcn_global_load_lds((const void*)(rp + off),
                                            (lds_void_t*)(reinterpret_cast<unsigned int*>(lb) + 64 * k), 4, 0, 0);
       }
     };
@@ -271,10 +276,10 @@ __global__ void __launch_bounds__(64)
       for (int k = 0; k < KSA; ++k) {
         const int d = lane + 64 * k;
         const bool ok = (k < KSA - 1 || d < NAUXDW) && x0 + d / DPE < a.n0;
-        if (ok)
+        if (ok || lane == 0)
           __builtin_amdgcn_global_load_lds(
-              (const void*)(rp + d), (lds_void_t*)(reinterpret_cast<unsigned int*>(ringa + slot * TXW) + 64 * k), 4,
-              0, 0);
+              (const void*)(rp + (ok ? d : 0)),
+              (lds_void_t*)(reinterpret_cast<unsigned int*>(ringa + slot * TXW) + 64 * k), 4, 0, 0);
       }
     }
   };

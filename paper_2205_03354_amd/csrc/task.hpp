@@ -1,0 +1,110 @@
+// A Krylov solve as a resumable state machine.
+//
+// A SolveTask owns the device state of one biharmonic BVP or Cahn-Hilliard
+// step (workspace vectors, scalars, partial sums) and advances it in chunks:
+// every call enqueues the next chunk of work on the task's stream (a block of
+// CG iterations, replayed from a captured hipGraph, or a true-residual
+// sweep) followed by a copy of the scalar block to pinned host memory, and
+// returns. Once that copy has landed the owner calls advance() again. The
+// blocking entry points loop start/advance with a stream synchronisation;
+// the request server interleaves many tasks on separate streams.
+#pragma once
+
+#include "internal.hpp"
+
+namespace sc {
+
+enum TaskKind : int { TASK_BVP = 0, TASK_CH = 1 };
+
+// A read-only FP64 grid view: `p` addresses interior element (0,0,0).
+struct GridView {
+  const double* p = nullptr;
+  int64_t pitch = 0;
+  int64_t zpitch = 0;
+};
+
+struct TaskSpec {
+  int kind = TASK_BVP;
+  int dim = 2;
+  int64_t n[3] = {1, 1, 1};
+  KStencil ksA;        // the operator A (weights scaled by h^-p)
+  KStencil ksL;        // TASK_CH: the Laplacian (scaled by h^-2)
+  double dt = 0.0;     // TASK_CH
+  double S = 0.0;      // TASK_CH
+  sc_solve_opts o{};
+};
+
+// Device bytes a task of this shape holds while it is alive.
+size_t task_footprint(const TaskSpec& spec);
+
+class SolveTask {
+ public:
+  SolveTask() = default;
+  SolveTask(const SolveTask&) = delete;
+  SolveTask& operator=(const SolveTask&) = delete;
+  ~SolveTask();
+
+  // Allocate and clear the workspace (enqueued on `st`).
+  sc_status init(const TaskSpec& spec, hipStream_t st);
+  // x0 := u0; right-hand side (BVP: f - A g_ring, g may be null; CH: from
+  // x0); first true residual; scalars to the host.
+  sc_status start(const GridView& u0, const GridView& f, const GridView* g);
+  // The previously enqueued chunk has completed: decide, enqueue the next
+  // chunk. *done = true when the solve has finished (see status()).
+  sc_status advance(bool* done);
+  // x -> dst (device FP64 view).
+  sc_status enqueue_copy_out(double* dst, int64_t pitch, int64_t zpitch);
+
+  sc_status status() const { return status_; }
+  const sc_solve_stats& stats() const { return stats_; }
+  hipStream_t stream() const { return st_; }
+  size_t footprint() const { return bytes_; }
+
+ private:
+  enum Phase { P_NONE, P_CHECK64, P_ITER64, P_FINAL, P_OUTER, P_INNER, P_DONE };
+  struct Vec {
+    void* alloc = nullptr;
+    void* base = nullptr;
+    Layout lay;
+  };
+  sc_status make(Vec* v, int dtype);
+  sc_status enqueue_block(bool f32);
+  sc_status enqueue_residual(int flag);
+  sc_status enqueue_read(bool both);
+  void finish(sc_status s);
+  sc_status sweep(int kind, int dtype, const KStencil& ks, const void* in, const Layout* lin, const void* in2,
+                  const void* aux, void* out, void* out2, const Layout& lout, int flag, double c0, double c1,
+                  double c2, DevScalars* sc, const GridView* in_view = nullptr, const GridView* aux_view = nullptr);
+
+  TaskSpec spec_;
+  bool periodic_ = false;
+  bool f32_ = false;
+  int halo_ = 0;
+  hipStream_t st_ = nullptr;
+  Vec x_, b_, r64_, r32_, d32_, p_[2], q_;
+  DevScalars* d64_ = nullptr;
+  DevScalars* d32s_ = nullptr;
+  DevScalars* h64_ = nullptr;
+  DevScalars* h32_ = nullptr;
+  double* partials_ = nullptr;
+  void* dev_block_ = nullptr;
+  std::vector<void*> allocs_;
+  size_t bytes_ = 0;
+  int cur_ = 0;
+  hipGraphExec_t graph_[2] = {nullptr, nullptr};  // [0] FP64 block, [1] FP32 block
+  int graph_k_[2] = {0, 0};
+  Phase phase_ = P_NONE;
+  sc_status pending_ = SC_OK;
+  sc_status status_ = SC_OK;
+  int outer_ = 0;
+  int stalled_ = 0;
+  double best_ = 0.0;
+  long long inner_start_ = 0;
+  sc_solve_stats stats_{};
+};
+
+// Pinned host slots for scalar read-back (one pair per live task).
+DevScalars* pinned_pair_alloc();
+void pinned_pair_free(DevScalars* p);
+
+}  // namespace sc
