@@ -33,6 +33,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# serving stream (sizes scaled down from 64..2048 / 32..192: without a
+# preconditioner the largest BVPs take tens of seconds each)
+SERVE_BVP_NODES = (33, 193)
+SERVE_CH_SIDE = (32, 96)
+SERVE_SLOTS = 16
+SERVE_LOAD = 0.7
 N_GRID = 4097
 PAIRS = 4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply2d_33pt_4097_f64_traffic.txt")
@@ -101,7 +107,8 @@ def solver_bench(native, torch, reps: int):
     f = torch.from_numpy(bvp.f).to(dev)
     g = torch.from_numpy(bvp.g).to(dev)
     op = stencils.biharmonic(2)
-    for name, prec in (("f64", native.SC_PREC_F64), ("f32_ir", native.SC_PREC_F32_IR)):
+    for name, prec in (("f64", native.SC_PREC_F64), ("f32_ir", native.SC_PREC_F32_IR),
+                       ("f32_ru", native.SC_PREC_F32_RU)):
         lat = []
         its = 0
         rel = 0.0
@@ -131,7 +138,8 @@ def ch_bench(native, torch, steps: int):
     h = 1.0 / N
     out = {}
     L = stencils.laplacian(2)
-    for name, prec in (("f64", native.SC_PREC_F64), ("f32_ir", native.SC_PREC_F32_IR)):
+    for name, prec in (("f64", native.SC_PREC_F64), ("f32_ir", native.SC_PREC_F32_IR),
+                       ("f32_ru", native.SC_PREC_F32_RU)):
         u = torch.from_numpy(S.zero_mean_uniform((N, N), seed=0)).to(dev)
         native.ch_step(L, u, h, 4 * h, 0.1 * h * h, 2.0, precision=prec)  # warm-up
         torch.cuda.synchronize()
@@ -145,12 +153,154 @@ def ch_bench(native, torch, steps: int):
     return {"workload": "Cahn-Hilliard step, 1024^2 periodic, eps=4h, dt=0.1h^2, S=2, to 1e-10", **out}
 
 
+def _pct(vals, q):
+    v = sorted(vals)
+    return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
+
+
+def serve_workload(n_req: int, seed: int = 5):
+    """The serving stream's requests: 60% 2D biharmonic BVPs, 40% single 3D
+    Cahn-Hilliard steps, sides log-uniform in the stated ranges (seeded)."""
+    import numpy as np
+
+    import synthetic as S
+
+    g = S.rng(seed)
+    reqs = []
+    for i in range(n_req):
+        if g.uniform() < 0.6:
+            N = int(round(math.exp(g.uniform(math.log(SERVE_BVP_NODES[0]), math.log(SERVE_BVP_NODES[1])))))
+            reqs.append(("bvp", N, S.biharmonic_bvp(2, N)))
+        else:
+            n = int(round(math.exp(g.uniform(math.log(SERVE_CH_SIDE[0]), math.log(SERVE_CH_SIDE[1])))))
+            h = 1.0 / n
+            u0 = S.zero_mean_uniform((n, n, n), seed=1000 + i)
+            reqs.append(("ch", n, (u0, (h, 4 * h, 0.1 * h * h, 2.0))))
+    return reqs
+
+
+def serve_bench(native, torch, n_req: int):
+    """Continuous batching vs one-at-a-time blocking FP64 solves on the same
+    request stream. Latency = completion - arrival; the arrival rate is a
+    fixed fraction of the served system's saturated rate (closed-loop pre-run)."""
+    import numpy as np
+
+    from paper_2205_03354_amd import stencils
+
+    dev = torch.device("cuda:0")
+    ops = {"bvp": stencils.biharmonic(2), "ch": stencils.laplacian(3)}
+    reqs = serve_workload(n_req)
+    out = {"workload": (f"{n_req} requests: 60% 2D biharmonic BVPs, nodes log-uniform in "
+                        f"{SERVE_BVP_NODES[0]}..{SERVE_BVP_NODES[1]}; 40% single 3D Cahn-Hilliard steps, "
+                        f"side log-uniform in {SERVE_CH_SIDE[0]}..{SERVE_CH_SIDE[1]} (eps=4h, dt=0.1h^2, S=2); "
+                        "all to a 1e-10 true relative residual"),
+           "load_factor": SERVE_LOAD}
+
+    def progress(msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
+    # one-at-a-time: blocking FP64 solves, service time of each request
+    progress(f"one-at-a-time FP64 over {n_req} requests")
+    service = []
+    ref = []
+    for kind, n, data in reqs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "bvp":
+            f = torch.from_numpy(data.f).to(dev)
+            gg = torch.from_numpy(data.g).to(dev)
+            u = torch.zeros_like(f)
+            native.solve_biharmonic(ops["bvp"], data.h, f, u, g=gg, g_halo=data.halo, tol=1e-10)
+        else:
+            u0, prm = data
+            u = torch.from_numpy(u0).to(dev)
+            native.ch_step(ops["ch"], u, *prm, tol=1e-10)
+        res = u.cpu().numpy()
+        service.append(time.perf_counter() - t0)
+        ref.append(res)
+
+    def run_server(precision, arrivals):
+        # precision: one sc_precision for every request, or a dict by kind
+        per_kind = precision if isinstance(precision, dict) else {"bvp": precision, "ch": precision}
+        srv = native.Server(max_slots=SERVE_SLOTS, tol=1e-10)
+        try:
+            t_base = None
+            ids = []
+            got = {}
+            t0 = time.perf_counter()
+            for k, (kind, n, data) in enumerate(reqs):
+                if arrivals is not None:
+                    while time.perf_counter() - t0 < arrivals[k]:
+                        for r in srv.poll(wait_ms=0):
+                            got[r["id"]] = r
+                        time.sleep(0.0002)
+                if kind == "bvp":
+                    rid = srv.submit_bvp(ops["bvp"], data.h, data.f, g=data.g, precision=per_kind["bvp"])
+                else:
+                    u0, prm = data
+                    rid = srv.submit_ch(ops["ch"], u0, *prm, precision=per_kind["ch"])
+                ids.append(rid)
+            while len(got) < len(ids):
+                for r in srv.poll(wait_ms=20):
+                    got[r["id"]] = r
+            wall = time.perf_counter() - t0
+            res = [got[i] for i in ids]
+            arrays = [srv.result_array(i) for i in ids]
+        finally:
+            srv.close()
+        return wall, res, arrays
+
+    # closed loop (all queued at once): the served system's saturated rate
+    progress("closed-loop served run")
+    wall_sat, _, _ = run_server(native.SC_PREC_F64, None)
+    rate = SERVE_LOAD * n_req / wall_sat
+    arr = np.cumsum(np.random.Generator(np.random.PCG64(11)).exponential(1.0 / rate, size=n_req))
+    arr -= arr[0]
+    out["arrival_rate_per_s"] = round(rate, 2)
+    out["saturated_solves_per_s"] = round(n_req / wall_sat, 2)
+
+    # one-at-a-time FIFO at the same arrival times
+    done_t, lat = 0.0, []
+    for k in range(n_req):
+        start = max(arr[k], done_t)
+        done_t = start + service[k]
+        lat.append(done_t - arr[k])
+    out["one_at_a_time_f64"] = {"solves_per_s": round(n_req / sum(service), 2),
+                                "p50_ms": round(1e3 * _pct(lat, 0.5), 2), "p99_ms": round(1e3 * _pct(lat, 0.99), 2),
+                                "makespan_s": round(done_t, 3)}
+    # FP32 refinement pays only where the operator is well conditioned: the
+    # Cahn-Hilliard step (condition number ~1e2) but not the biharmonic BVP
+    # (~n^4), so the mixed configuration serves BVPs in FP64
+    mixed = {"bvp": native.SC_PREC_F64, "ch": native.SC_PREC_F32_IR}
+    for name, prec in (("served_f64", native.SC_PREC_F64), ("served_mixed", mixed)):
+        progress(f"open-loop {name} at {rate:.1f} requests/s")
+        wall, res, arrays = run_server(prec, arr)
+        lat = [r["t_done"] - r["t_submit"] for r in res]
+        its = sum(r["iterations"] for r in res)
+        entry = {"solves_per_s": round(n_req / wall, 2), "p50_ms": round(1e3 * _pct(lat, 0.5), 2),
+                 "p99_ms": round(1e3 * _pct(lat, 0.99), 2), "makespan_s": round(wall, 3),
+                 "total_cg_iterations": int(its),
+                 "failed": sum(1 for r in res if r["status"] != native.SC_OK)}
+        if isinstance(prec, dict):
+            entry["precision"] = "BVP FP64, CH FP32 CG + FP64 refinement"
+        if prec == native.SC_PREC_F64:
+            entry["identical_to_one_at_a_time"] = all(np.array_equal(a, b) for a, b in zip(arrays, ref))
+        else:
+            entry["max_rel_diff_vs_f64"] = float(max(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+                                                     for a, b in zip(arrays, ref)))
+        out[name] = entry
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-extras", action="store_true", help="only the timed apply (for profiling)")
+    ap.add_argument("--extras", default="solves,ch,serve,cpu",
+                    help="comma-separated extras to run after the timed apply")
+    ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain device copies of the same 4097^2 FP64 arrays (calibrates the "
                          "HBM byte counters against a kernel of known traffic)")
@@ -194,21 +344,19 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    # whole-job time: K steps between two synchronisations
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # kernel duration: events recorded on the stream the kernel runs on,
-    # immediately before and after each launch (host gaps excluded)
+    # whole-job time: K steps between two synchronisations. The kernel's own
+    # duration comes from events recorded immediately before and after each
+    # launch on the stream it runs on (torch's current stream), so host gaps
+    # between launches are excluded from it.
     ev_s = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ev_e = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t0 = time.perf_counter()
     for i in range(args.steps):
         ev_s[i].record()
         step(i)
         ev_e[i].record()
     torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     kern_ms = [ev_s[i].elapsed_time(ev_e[i]) for i in range(args.steps)]
     avg_kernel_ms = sum(kern_ms) / len(kern_ms)
 
@@ -244,9 +392,14 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
     }
-    if not args.no_extras:
+    extras = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
+    if "solves" in extras:
         result["solves"] = solver_bench(native, torch, reps=20)
+    if "ch" in extras:
         result["ch"] = ch_bench(native, torch, steps=5)
+    if "serve" in extras:
+        result["serve"] = serve_bench(native, torch, args.serve_requests)
+    if "cpu" in extras:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
 

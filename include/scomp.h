@@ -63,10 +63,22 @@ typedef enum sc_dtype { SC_F64 = 0, SC_F32 = 1 } sc_dtype;
  * grid.halo stored around the interior (which must be >= the radius). */
 typedef enum sc_bc { SC_BC_PERIODIC = 0, SC_BC_HALO = 1 } sc_bc;
 
-/* Arithmetic of the Krylov solves: plain FP64 CG, or FP32 CG (FP32 vectors
- * and applies, FP64 dot-product accumulators) inside FP64 iterative
- * refinement on the true residual. */
-typedef enum sc_precision { SC_PREC_F64 = 0, SC_PREC_F32_IR = 1 } sc_precision;
+/* Arithmetic of the Krylov solves.
+ *   SC_PREC_F64     plain FP64 CG.
+ *   SC_PREC_F32_IR  FP32 CG (FP32 vectors and applies, FP64 dot-product
+ *                   accumulators) inside FP64 iterative refinement: each
+ *                   outer step solves A d = r / ||r|| from scratch to a
+ *                   relative reduction inner_tol, then x += ||r|| d in FP64
+ *                   and r = b - A x is recomputed in FP64.
+ *   SC_PREC_F32_RU  FP32 CG with reliable updates (Sleijpen and van der
+ *                   Vorst, 1996): whenever the FP32 recursive residual has
+ *                   dropped by inner_tol since the last update, the FP32
+ *                   solution increment is folded into the FP64 solution, the
+ *                   residual is replaced by the FP64 true residual, and the
+ *                   FP32 recurrence continues with its search direction
+ *                   instead of restarting. Same precisions as SC_PREC_F32_IR.
+ * Both mixed modes stop on the FP64 true residual. */
+typedef enum sc_precision { SC_PREC_F64 = 0, SC_PREC_F32_IR = 1, SC_PREC_F32_RU = 2 } sc_precision;
 
 typedef struct sc_stencil sc_stencil;
 
@@ -170,9 +182,11 @@ sc_status sc_apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc
 
 typedef struct sc_solve_opts {
   double tol;           /* target true relative residual ||b - A x||_2 / ||b||_2 (FP64) */
-  int64_t max_iter;     /* cap on CG iterations (inner iterations under SC_PREC_F32_IR) */
+  int64_t max_iter;     /* cap on CG iterations (FP32 iterations in the mixed modes) */
   int32_t precision;    /* sc_precision */
-  double inner_tol;     /* SC_PREC_F32_IR: residual reduction asked of each FP32 solve */
+  double inner_tol;     /* mixed modes: FP32 residual reduction per stretch (per
+                           refinement solve, or between reliable updates);
+                           <= 0 selects 1e-4 (F32_IR) or 0.1 (F32_RU) */
   int32_t check_every;  /* CG iterations launched between host convergence checks */
   int32_t use_graph;    /* 1: replay each block of check_every iterations from a
                            captured hipGraph (check_every even); 0: plain launches */
@@ -187,7 +201,7 @@ typedef struct sc_solve_stats {
 } sc_solve_stats;
 
 /* Fill opts with defaults: tol 1e-10, max_iter 10^7, SC_PREC_F64,
- * inner_tol 1e-4, check_every 64, use_graph 1. */
+ * inner_tol 0 (the precision's default), check_every 64, use_graph 1. */
 void sc_solve_opts_default(sc_solve_opts* opts);
 
 /*

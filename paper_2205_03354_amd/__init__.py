@@ -11,6 +11,7 @@ from ._native import (  # noqa: F401
     SC_BC_HALO,
     SC_BC_PERIODIC,
     SC_PREC_F32_IR,
+    SC_PREC_F32_RU,
     SC_PREC_F64,
     SC_REQ_BVP,
     SC_REQ_CH_STEP,

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libscomp.so")
 SC_REQ_BVP, SC_REQ_CH_STEP = 0, 1
 SC_F64, SC_F32 = 0, 1
 SC_BC_PERIODIC, SC_BC_HALO = 0, 1
-SC_PREC_F64, SC_PREC_F32_IR = 0, 1
+SC_PREC_F64, SC_PREC_F32_IR, SC_PREC_F32_RU = 0, 1, 2
 
 EXPORTED = (
     "sc_stencil_create", "sc_compose_stencil", "sc_stencil_lincomb", "sc_stencil_get",
@@ -293,7 +293,7 @@ def _stats(s: SCSolveStats, status: int) -> SolveStats:
 
 
 def solve_biharmonic(op: Stencil, h: float, f, u, g=None, g_halo: int = 0, tol: float = 1e-10,
-                     max_iter: int = 10**7, precision: int = SC_PREC_F64, inner_tol: float = 1e-4,
+                     max_iter: int = 10**7, precision: int = SC_PREC_F64, inner_tol: float = 0.0,
                      check_every: int = 64, use_graph: bool = True, raise_on_error: bool = True,
                      stream=None) -> SolveStats:
     """A u = f at the unknowns with the ring prescribed by g (see scomp.h)."""
@@ -309,7 +309,7 @@ def solve_biharmonic(op: Stencil, h: float, f, u, g=None, g_halo: int = 0, tol: 
 
 
 def ch_step(lap: Stencil, u, h: float, eps: float, dt: float, S: float, tol: float = 1e-10,
-            max_iter: int = 10**6, precision: int = SC_PREC_F64, inner_tol: float = 1e-4,
+            max_iter: int = 10**6, precision: int = SC_PREC_F64, inner_tol: float = 0.0,
             check_every: int = 32, use_graph: bool = True, raise_on_error: bool = True,
             stream=None) -> SolveStats:
     """One linearly stabilised semi-implicit Cahn-Hilliard step, in place on u."""
@@ -341,7 +341,7 @@ class Server:
     ``result_array(id)`` once its result has been polled."""
 
     def __init__(self, hbm_budget: int = 0, max_slots: int = 16, tol: float = 1e-10,
-                 precision: int = SC_PREC_F64, inner_tol: float = 1e-4, check_every: int = 64,
+                 precision: int = SC_PREC_F64, inner_tol: float = 0.0, check_every: int = 64,
                  use_graph: bool = True, max_iter: int = 10**7, fake_device: bool = False):
         o = SCServerOpts()
         o.hbm_budget = int(hbm_budget)

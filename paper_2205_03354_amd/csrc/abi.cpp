@@ -102,7 +102,7 @@ void sc_solve_opts_default(sc_solve_opts* o) {
   o->tol = 1e-10;
   o->max_iter = 10000000;
   o->precision = SC_PREC_F64;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 0.0;
   o->check_every = 64;
   o->use_graph = 1;
 }

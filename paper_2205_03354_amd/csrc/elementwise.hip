@@ -58,8 +58,10 @@ __global__ void __launch_bounds__(kNT)
     ir_prepare_kernel(const double* __restrict__ r64, int64_t p64, int64_t z64, float* __restrict__ r32,
                       float* __restrict__ d32, int64_t p32, int64_t z32, int64_t n0, int64_t n1,
                       int64_t n2, const DevScalars* s64, DevScalars* s32, double inner_tol2,
-                      double* partials) {
-  const double inv = 1.0 / sqrt(s64->rr_true);
+                      int keep_direction, double* partials) {
+  // A restart scales by the current ||r||; a reliable update keeps the scale
+  // of the stretch's restart so that the FP32 direction p stays consistent.
+  const double inv = keep_direction ? 1.0 / s32->scale : 1.0 / sqrt(s64->rr_true);
   const RowRange rr = block_rows(n1 * n2);
   double dot = 0.0;
   for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
@@ -73,9 +75,16 @@ __global__ void __launch_bounds__(kNT)
     }
   }
   grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s32->ticket, [&](double total) {
+    if (keep_direction) {
+      // beta = <r', r'> / <r_old, r_old> with r' the replaced residual;
+      // the last update left beta = rr / rr_old and rr.
+      s32->beta = s32->rr > 0.0 ? s32->beta * (total / s32->rr) : 0.0;
+    } else {
+      s32->scale = sqrt(s64->rr_true);
+      s32->beta = 0.0;
+    }
     s32->rr = total;
     s32->rr_stop = inner_tol2 * total;
-    s32->beta = 0.0;
     s32->done = total > 0.0 ? 0 : 1;
   });
 }
@@ -83,8 +92,8 @@ __global__ void __launch_bounds__(kNT)
 __global__ void __launch_bounds__(kNT)
     ir_update_kernel(double* __restrict__ x64, int64_t p64, int64_t z64, const float* __restrict__ d32,
                      int64_t p32, int64_t z32, int64_t n0, int64_t n1, int64_t n2,
-                     const DevScalars* s64) {
-  const double scale = sqrt(s64->rr_true);
+                     const DevScalars* s32) {
+  const double scale = s32->scale;
   const RowRange rr = block_rows(n1 * n2);
   for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
     const int64_t o64 = row_offset(rho, n1, p64, z64);
@@ -188,18 +197,19 @@ hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const vo
 
 hipError_t launch_ir_prepare(const double* r64, const Layout& l64, float* r32, float* d32,
                              const Layout& l32, const int64_t* n, DevScalars* s64, DevScalars* s32,
-                             double inner_tol2, double* partials, hipStream_t st) {
+                             double inner_tol2, int keep_direction, double* partials, hipStream_t st) {
   const int nb = elem_blocks(n);
   hipLaunchKernelGGL(ir_prepare_kernel, dim3(nb), dim3(kNT), 0, st, r64, l64.pitch, l64.zpitch, r32,
-                     d32, l32.pitch, l32.zpitch, n[0], n[1], n[2], s64, s32, inner_tol2, partials);
+                     d32, l32.pitch, l32.zpitch, n[0], n[1], n[2], s64, s32, inner_tol2, keep_direction,
+                     partials);
   return hipGetLastError();
 }
 
 hipError_t launch_ir_update(double* x64, const Layout& l64, const float* d32, const Layout& l32,
-                            const int64_t* n, const DevScalars* s64, hipStream_t st) {
+                            const int64_t* n, const DevScalars* s32, hipStream_t st) {
   const int nb = elem_blocks(n);
   hipLaunchKernelGGL(ir_update_kernel, dim3(nb), dim3(kNT), 0, st, x64, l64.pitch, l64.zpitch, d32,
-                     l32.pitch, l32.zpitch, n[0], n[1], n[2], s64);
+                     l32.pitch, l32.zpitch, n[0], n[1], n[2], s32);
   return hipGetLastError();
 }
 

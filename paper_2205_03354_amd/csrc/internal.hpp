@@ -123,15 +123,17 @@ constexpr int kElemBlocks = 1024;  // blocks of the element-wise kernels
 hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
                             const Layout& lay, const int64_t* n, DevScalars* s, double* partials,
                             hipStream_t st);
-// r32 = r64 / sqrt(s64->rr_true); d32 = 0; inner scalars (re)started with
-// rr_stop = inner_tol^2 <r32, r32>.
+// r32 = r64 / s; d32 = 0; rr = <r32, r32>, rr_stop = inner_tol^2 rr. A
+// restart (keep_direction 0) sets s = sqrt(s64->rr_true) and beta = 0; a
+// reliable update (keep_direction 1) keeps s and rescales beta so that the
+// next direction continues the FP32 recurrence from the replaced residual.
 hipError_t launch_ir_prepare(const double* r64, const Layout& l64, float* r32, float* d32,
                              const Layout& l32, const int64_t* n, DevScalars* s64,
-                             DevScalars* s32, double inner_tol2, double* partials,
-                             hipStream_t st);
-// x64 += sqrt(s64->rr_true) * d32
+                             DevScalars* s32, double inner_tol2, int keep_direction,
+                             double* partials, hipStream_t st);
+// x64 += s32->scale * d32
 hipError_t launch_ir_update(double* x64, const Layout& l64, const float* d32, const Layout& l32,
-                            const int64_t* n, const DevScalars* s64, hipStream_t st);
+                            const int64_t* n, const DevScalars* s32, hipStream_t st);
 // Copy the interior of one FP64 grid view to another.
 hipError_t launch_copy(const double* src, int64_t sp, int64_t sz, double* dst, int64_t dp,
                        int64_t dz, const int64_t* n, hipStream_t st);
@@ -165,6 +167,7 @@ void server_destroy(sc_server* s);
 sc_status check_grid(const sc_grid* g, const char* what);
 void* interior(const sc_grid* g);
 void fill_opts(const sc_solve_opts* in, sc_solve_opts* o);
+sc_status check_precision(int precision);
 sc_status check_ch(const sc_stencil* lap, const sc_ch_params* prm, int dim);
 sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* ksA, KStencil* ksL);
 

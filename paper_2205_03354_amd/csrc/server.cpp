@@ -68,6 +68,7 @@ int64_t ring_points(const TaskSpec& sp, int halo) {
 
 struct sc_server {
   sc_server_opts opts{};
+  bool inner_tol_set = false;  // the caller chose inner_tol (else each precision's default)
   size_t budget = 0;
   std::mutex mu;
   std::condition_variable cv_done;   // results available
@@ -317,7 +318,14 @@ sc_status make_spec(const sc_server* S, const sc_request* r, Request* q) {
   }
   TaskSpec& sp = q->spec;
   sp.o = S->opts.solve;
-  if (r->precision == SC_PREC_F64 || r->precision == SC_PREC_F32_IR) sp.o.precision = r->precision;
+  if (r->precision != -1) {
+    sc_status ps = check_precision(r->precision);
+    if (ps != SC_OK) return ps;
+    sc_solve_opts o = S->opts.solve;
+    o.precision = r->precision;
+    if (!S->inner_tol_set) o.inner_tol = 0.0;  // the default of the request's precision
+    fill_opts(&o, &sp.o);
+  }
   sp.dim = r->dim;
   for (int a = 0; a < 3; ++a) sp.n[a] = r->n[a];
   const int64_t np = r->n[0] * r->n[1] * r->n[2];
@@ -374,6 +382,8 @@ sc_status server_create(const sc_server_opts* opts, sc_server** out) {
   auto S = std::make_unique<sc_server>();
   S->opts = *opts;
   fill_opts(&opts->solve, &S->opts.solve);
+  S->inner_tol_set = opts->solve.inner_tol > 0;
+  if (check_precision(S->opts.solve.precision) != SC_OK) return SC_EINVAL;
   S->slots.resize(opts->max_slots);
   if (!opts->fake_device) {
     SC_HIP_CHECK(hipGetDevice(&S->device));

@@ -154,12 +154,12 @@ void pinned_pair_free(DevScalars* p) {
 
 size_t task_footprint(const TaskSpec& sp) {
   const int halo = sp.kind == TASK_BVP ? sp.ksA.R : 0;
-  const bool f32 = sp.o.precision == SC_PREC_F32_IR;
+  const bool f32 = sp.o.precision != SC_PREC_F64;
   size_t b = 0;
   const size_t v64 = vec_bytes(sp.dim, sp.n, halo, SC_F64);
   const size_t v32 = vec_bytes(sp.dim, sp.n, halo, SC_F32);
   if (f32)
-    b = 3 * v64 + 5 * v32;  // x b r64 | r d p0 p1 q
+    b = 6 * v64 + 5 * v32;  // x b r64 (+ p0 p1 q if it falls back to FP64) | r d p0 p1 q
   else
     b = 6 * v64;            // x b r p0 p1 q
   b += 4096 + (size_t)partial_slots(sp) * 3 * sizeof(double);
@@ -169,8 +169,9 @@ size_t task_footprint(const TaskSpec& sp) {
 // ------------------------------------------------------------------ task
 SolveTask::~SolveTask() {
   if (st_ && !allocs_.empty()) (void)hipStreamSynchronize(st_);
-  for (auto& g : graph_)
-    if (g) (void)hipGraphExecDestroy(g);
+  for (auto& gp : graph_)
+    for (auto& g : gp)
+      if (g) (void)hipGraphExecDestroy(g);
   for (void* p : allocs_) pool_free(p);
   if (h64_) pinned_pair_free(h64_);
 }
@@ -198,7 +199,9 @@ sc_status SolveTask::init(const TaskSpec& spec, hipStream_t st) {
   spec_ = spec;
   st_ = st;
   periodic_ = spec.kind == TASK_CH;
-  f32_ = spec.o.precision == SC_PREC_F32_IR;
+  f32_ = spec.o.precision != SC_PREC_F64;
+  ru_ = spec.o.precision == SC_PREC_F32_RU;
+  restart_ = true;
   halo_ = periodic_ ? 0 : spec.ksA.R;
   h64_ = pinned_pair_alloc();
   if (!h64_) {
@@ -287,7 +290,7 @@ sc_status SolveTask::enqueue_residual(int flag) {
 }
 
 // K CG iterations (direction sweep + update each), replayed from a graph
-// captured on first use when K is even and the ping-pong parity matches.
+// captured on first use, one graph per ping-pong parity of the p buffers.
 sc_status SolveTask::enqueue_block(bool f32) {
   const int dtype = f32 ? SC_F32 : SC_F64;
   DevScalars* ds = f32 ? d32s_ : d64_;
@@ -297,6 +300,8 @@ sc_status SolveTask::enqueue_block(bool f32) {
   const int gi = f32 ? 1 : 0;
   const int K = std::max(1, spec_.o.check_every);
   const int64_t left = spec_.o.max_iter - hs->iter;
+  block_cur0_ = cur_;
+  block_iter0_ = hs->iter;
   auto one = [&]() -> sc_status {
     sc_status s = sweep(K_CGDIR, dtype, spec_.ksA, r.base, &r.lay, p_[cur_].base, nullptr, p_[1 - cur_].base,
                         q_.base, r.lay, 0, 0, 0, 0, ds);
@@ -306,15 +311,16 @@ sc_status SolveTask::enqueue_block(bool f32) {
     cur_ = 1 - cur_;
     return SC_OK;
   };
-  const bool graph_ok = spec_.o.use_graph && K % 2 == 0 && left >= K && cur_ == 0;
-  if (graph_ok) {
-    if (!graph_[gi]) {
-      hipGraph_t g = nullptr;
+  if (spec_.o.use_graph && left >= K) {
+    hipGraphExec_t& ge = graph_[gi][cur_];
+    const int cur0 = cur_;
+    if (!ge) {
       SC_HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
       sc_status s = SC_OK;
       for (int k = 0; k < K && s == SC_OK; ++k) s = one();
       hipGraph_t captured = nullptr;
       const hipError_t e = hipStreamEndCapture(st_, &captured);
+      cur_ = cur0;
       if (s != SC_OK) {
         if (captured) (void)hipGraphDestroy(captured);
         return s;
@@ -323,17 +329,16 @@ sc_status SolveTask::enqueue_block(bool f32) {
         set_error("graph capture failed: %s", hipGetErrorString(e));
         return SC_EDEVICE;
       }
-      g = captured;
-      const hipError_t ei = hipGraphInstantiate(&graph_[gi], g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
+      const hipError_t ei = hipGraphInstantiate(&ge, captured, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(captured);
       if (ei != hipSuccess) {
-        graph_[gi] = nullptr;
+        ge = nullptr;
         set_error("graph instantiation failed: %s", hipGetErrorString(ei));
         return SC_EDEVICE;
       }
-      graph_k_[gi] = K;
     }
-    SC_HIP_CHECK(hipGraphLaunch(graph_[gi], st_));
+    SC_HIP_CHECK(hipGraphLaunch(ge, st_));
+    cur_ = cur0 ^ (K & 1);
   } else {
     const int64_t k_run = std::min<int64_t>(K, left);
     for (int64_t k = 0; k < k_run; ++k) {
@@ -377,10 +382,31 @@ sc_status SolveTask::start(const GridView& u0, const GridView& f, const GridView
 void SolveTask::finish(sc_status s) {
   status_ = s;
   phase_ = P_DONE;
-  stats_.iterations = f32_ ? h32_->iter : h64_->iter;
+  stats_.iterations = h64_->iter + (spec_.o.precision != SC_PREC_F64 ? h32_->iter : 0);
   stats_.outer = outer_;
   stats_.bnorm = std::sqrt(h64_->bb);
   stats_.rel_residual = h64_->bb > 0 ? std::sqrt(h64_->rr_true / h64_->bb) : 0.0;
+}
+
+// The FP32 stretches stopped reducing the FP64 residual (the operator is
+// too ill-conditioned for an FP32 Krylov recurrence): continue with FP64 CG
+// from the current x, in FP64 direction buffers allocated now.
+sc_status SolveTask::fall_back_to_f64() {
+  sc_status s;
+  Vec p0, p1, q;
+  if ((s = make(&p0, SC_F64)) != SC_OK || (s = make(&p1, SC_F64)) != SC_OK || (s = make(&q, SC_F64)) != SC_OK)
+    return s;
+  p_[0] = p0;
+  p_[1] = p1;
+  q_ = q;
+  cur_ = 0;
+  f32_ = false;
+  fell_back_ = true;
+  stalled_ = 0;
+  best_ = HUGE_VAL;
+  if ((s = enqueue_residual(1)) != SC_OK || (s = enqueue_read(false)) != SC_OK) return s;
+  phase_ = P_CHECK64;
+  return SC_OK;
 }
 
 sc_status SolveTask::advance(bool* done) {
@@ -439,22 +465,42 @@ sc_status SolveTask::advance(bool* done) {
         set_error("refinement did not reach the tolerance in %lld inner iterations", (long long)o.max_iter);
         finish(SC_ENOTCONV);
       } else if (stagnated()) {
-        set_error("refinement stagnated at relative residual %g", std::sqrt(h64_->rr_true / h64_->bb));
-        finish(SC_ENOTCONV);
+        return fall_back_to_f64();
       } else {
+        const int keep = (ru_ && !restart_) ? 1 : 0;
         SC_HIP_CHECK(launch_ir_prepare((const double*)r64_.base, r64_.lay, (float*)r32_.base, (float*)d32_.base,
-                                       r32_.lay, spec_.n, d64_, d32s_, o.inner_tol * o.inner_tol, partials_, st_));
+                                       r32_.lay, spec_.n, d64_, d32s_, o.inner_tol * o.inner_tol, keep, partials_,
+                                       st_));
+        restart_ = false;
+        inner_keep_ = keep;
         inner_start_ = h32_->iter;
+        stretch_best_ = HUGE_VAL;
+        stretch_idle_ = 0;
         if ((s = enqueue_block(true)) != SC_OK) return s;
         phase_ = P_INNER;
       }
       break;
-    case P_INNER:
-      if (h32_->done == 2 && h32_->iter == inner_start_) {
-        set_error("FP32 CG breakdown at the first inner iteration (<p, Ap> = %g)", h32_->pq);
-        finish(SC_EBREAKDOWN);
-      } else if (h32_->done != 0 || h32_->iter >= o.max_iter) {
-        SC_HIP_CHECK(launch_ir_update((double*)x_.base, x_.lay, (const float*)d32_.base, d32_.lay, spec_.n, d64_, st_));
+    case P_INNER: {
+      const bool first_breakdown = h32_->done == 2 && h32_->iter == inner_start_ && !inner_keep_;
+      bool end = h32_->done != 0 || h32_->iter >= o.max_iter;
+      if (!end) {
+        // a stretch whose FP32 residual has not halved in 8 blocks ends early
+        if (h32_->rr < 0.25 * stretch_best_) {
+          stretch_best_ = h32_->rr;
+          stretch_idle_ = 0;
+        } else if (++stretch_idle_ >= 8) {
+          end = true;
+        }
+      }
+      if (first_breakdown) {
+        return fall_back_to_f64();  // FP32 lost positivity of <p, Ap> at once
+      } else if (end) {
+        // the latest direction sits in the buffer the executed iterations
+        // of the last block wrote (the skipped ones did not toggle it)
+        cur_ = block_cur0_ ^ (int)((h32_->iter - block_iter0_) & 1);
+        if (h32_->done == 2) restart_ = true;  // a lost direction: restart from p = r
+        SC_HIP_CHECK(launch_ir_update((double*)x_.base, x_.lay, (const float*)d32_.base, d32_.lay, spec_.n, d32s_,
+                                      st_));
         if ((s = enqueue_residual(0)) != SC_OK || (s = enqueue_read(true)) != SC_OK) return s;
         ++outer_;
         phase_ = P_OUTER;
@@ -462,6 +508,7 @@ sc_status SolveTask::advance(bool* done) {
         if ((s = enqueue_block(true)) != SC_OK) return s;
       }
       break;
+    }
     default:
       break;
   }
@@ -592,8 +639,16 @@ void fill_opts(const sc_solve_opts* in, sc_solve_opts* o) {
   if (in) *o = *in;
   if (!(o->tol > 0)) o->tol = 1e-10;
   if (o->max_iter <= 0) o->max_iter = 10000000;
-  if (!(o->inner_tol > 0)) o->inner_tol = 1e-4;
+  if (!(o->inner_tol > 0)) o->inner_tol = o->precision == SC_PREC_F32_RU ? 0.1 : 1e-4;
   if (o->check_every <= 0) o->check_every = 64;
+}
+
+sc_status check_precision(int precision) {
+  if (precision != SC_PREC_F64 && precision != SC_PREC_F32_IR && precision != SC_PREC_F32_RU) {
+    set_error("unknown precision %d", precision);
+    return SC_EINVAL;
+  }
+  return SC_OK;
 }
 
 // The operator of one Cahn-Hilliard step, I + dt eps^2 L o L - dt S L,
@@ -697,10 +752,7 @@ sc_status solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, con
   }
   TaskSpec sp;
   fill_opts(opts, &sp.o);
-  if (sp.o.precision != SC_PREC_F64 && sp.o.precision != SC_PREC_F32_IR) {
-    set_error("unknown precision %d", sp.o.precision);
-    return SC_EINVAL;
-  }
+  if ((r = check_precision(sp.o.precision)) != SC_OK) return r;
   if ((r = make_kstencil(op, h, &sp.ksA)) != SC_OK) return r;
   const int rad = sc_stencil_radius(op);
   if (gr && gr->halo < rad) {
@@ -739,6 +791,7 @@ sc_status ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_solve
   if ((r = check_ch(lap, prm, u->dim)) != SC_OK) return r;
   TaskSpec sp;
   fill_opts(opts, &sp.o);
+  if ((r = check_precision(sp.o.precision)) != SC_OK) return r;
   if ((r = ch_operator(lap, prm, &sp.ksA, &sp.ksL)) != SC_OK) return r;
   sp.kind = TASK_CH;
   sp.dim = u->dim;

@@ -71,6 +71,7 @@ class SolveTask {
   sc_status enqueue_block(bool f32);
   sc_status enqueue_residual(int flag);
   sc_status enqueue_read(bool both);
+  sc_status fall_back_to_f64();
   void finish(sc_status s);
   sc_status sweep(int kind, int dtype, const KStencil& ks, const void* in, const Layout* lin, const void* in2,
                   const void* aux, void* out, void* out2, const Layout& lout, int flag, double c0, double c1,
@@ -78,7 +79,9 @@ class SolveTask {
 
   TaskSpec spec_;
   bool periodic_ = false;
-  bool f32_ = false;
+  bool f32_ = false;   // FP32 inner iterations (refinement or reliable updates)
+  bool ru_ = false;    // reliable updates: keep the FP32 direction across replacements
+  bool restart_ = true;  // next FP32 stretch starts from p = r
   int halo_ = 0;
   hipStream_t st_ = nullptr;
   Vec x_, b_, r64_, r32_, d32_, p_[2], q_;
@@ -90,9 +93,10 @@ class SolveTask {
   void* dev_block_ = nullptr;
   std::vector<void*> allocs_;
   size_t bytes_ = 0;
-  int cur_ = 0;
-  hipGraphExec_t graph_[2] = {nullptr, nullptr};  // [0] FP64 block, [1] FP32 block
-  int graph_k_[2] = {0, 0};
+  int cur_ = 0;          // p_[cur_] holds the latest search direction
+  int block_cur0_ = 0;    // cur_ and the device iteration count when the
+  long long block_iter0_ = 0;  // last block was enqueued
+  hipGraphExec_t graph_[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [FP32][parity]
   Phase phase_ = P_NONE;
   sc_status pending_ = SC_OK;
   sc_status status_ = SC_OK;
@@ -100,6 +104,10 @@ class SolveTask {
   int stalled_ = 0;
   double best_ = 0.0;
   long long inner_start_ = 0;
+  int inner_keep_ = 0;    // the running FP32 stretch continued the previous direction
+  double stretch_best_ = 0.0;  // smallest FP32 recursive rr seen in the running stretch
+  int stretch_idle_ = 0;       // blocks since it last halved
+  bool fell_back_ = false;     // a mixed-precision solve that continued in FP64
   sc_solve_stats stats_{};
 };
 

@@ -50,10 +50,10 @@ def _blocking_ch(nat, lap, u0, h, eps, dt, Sst, precision, use_graph):
     return u.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32ir"])
-@pytest.mark.parametrize("check_every", [8, 64])
+@pytest.mark.parametrize("prec", ["f64", "f32ir", "f32ru"])
+@pytest.mark.parametrize("check_every", [7, 8, 64])
 def test_graph_blocks_bit_identical_bvp(nat, ops, prec, check_every):
-    precision = nat.SC_PREC_F64 if prec == "f64" else nat.SC_PREC_F32_IR
+    precision = {"f64": nat.SC_PREC_F64, "f32ir": nat.SC_PREC_F32_IR, "f32ru": nat.SC_PREC_F32_RU}[prec]
     bvp = S.biharmonic_bvp(2, 33)
     x0, s0 = _blocking_bvp(nat, ops[2], bvp, precision, False, check_every)
     # Several solves with graphs: each replays its captured block many times,
@@ -106,13 +106,15 @@ def _serve(nat, jobs, max_slots, **kw):
 def _job_mix(nat, ops):
     jobs = []
     for k, N in enumerate((17, 33, 65, 33, 17, 49)):
-        prec = nat.SC_PREC_F64 if k % 2 == 0 else nat.SC_PREC_F32_IR
+        prec = (nat.SC_PREC_F64, nat.SC_PREC_F32_IR, nat.SC_PREC_F32_RU)[k % 3]
         jobs.append(("bvp", ops[2], S.biharmonic_bvp(2, N), prec))
     jobs.append(("bvp", ops[3], S.biharmonic_bvp(3, 15), nat.SC_PREC_F64))
     jobs.append(("ch", ops["L2"], S.zero_mean_uniform((64, 64), seed=7), (1.0 / 64, 0.05, 1e-4, 2.0),
                  nat.SC_PREC_F64))
     jobs.append(("ch", ops["L3"], S.zero_mean_uniform((16, 16, 16), seed=8), (1.0 / 16, 0.1, 1e-3, 2.0),
                  nat.SC_PREC_F32_IR))
+    jobs.append(("ch", ops["L3"], S.zero_mean_uniform((20, 20, 20), seed=9), (1.0 / 20, 0.1, 1e-3, 2.0),
+                 nat.SC_PREC_F32_RU))
     return jobs
 
 

@@ -24,6 +24,8 @@ pytestmark = pytest.mark.gpu
 
 DEV = torch.device("cuda:0")
 
+_PREC = {"f64": lambda m: m.SC_PREC_F64, "f32ir": lambda m: m.SC_PREC_F32_IR, "f32ru": lambda m: m.SC_PREC_F32_RU}
+
 
 @pytest.fixture(scope="module")
 def native():
@@ -45,9 +47,9 @@ def _gpu_bvp(native, dim, size, precision, tol=1e-10, **kw):
 
 
 @pytest.mark.parametrize("N", [17, 33, 65])
-@pytest.mark.parametrize("prec", ["f64", "f32ir"])
+@pytest.mark.parametrize("prec", ["f64", "f32ir", "f32ru"])
 def test_bvp2d_parity(native, N, prec):
-    precision = native.SC_PREC_F64 if prec == "f64" else native.SC_PREC_F32_IR
+    precision = _PREC[prec](native)
     bvp, x, st = _gpu_bvp(native, 2, N, precision)
     op = R.biharmonic(2)
     b = OP.bvp_rhs(op, bvp.f, bvp.g, bvp.halo, bvp.h)
@@ -72,9 +74,9 @@ def test_bvp2d_second_order_on_gpu(native):
 
 
 @pytest.mark.parametrize("n", [7, 15, 31])
-@pytest.mark.parametrize("prec", ["f64", "f32ir"])
+@pytest.mark.parametrize("prec", ["f64", "f32ir", "f32ru"])
 def test_bvp3d_parity(native, n, prec):
-    precision = native.SC_PREC_F64 if prec == "f64" else native.SC_PREC_F32_IR
+    precision = _PREC[prec](native)
     bvp, x, st = _gpu_bvp(native, 3, n, precision)
     op = R.biharmonic(3)
     b = OP.bvp_rhs(op, bvp.f, bvp.g, bvp.halo, bvp.h)
@@ -134,9 +136,9 @@ def _ch_gpu(native, u_np, h, eps, dt, Sst, steps, precision, tol=1e-10):
 
 
 @pytest.mark.parametrize("dim,N", [(2, 64), (3, 16)])
-@pytest.mark.parametrize("prec", ["f64", "f32ir"])
+@pytest.mark.parametrize("prec", ["f64", "f32ir", "f32ru"])
 def test_ch_step_parity(native, dim, N, prec):
-    precision = native.SC_PREC_F64 if prec == "f64" else native.SC_PREC_F32_IR
+    precision = _PREC[prec](native)
     h = 1.0 / N
     eps, dt, Sst = 4 * h, 0.1 * h * h, 2.0
     u0 = S.zero_mean_uniform((N,) * dim, seed=3)
@@ -158,9 +160,9 @@ def test_ch_single_mode_closed_form_gpu(native):
     assert np.max(np.abs(ug - expect)) <= 1e-12
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32ir"])
+@pytest.mark.parametrize("prec", ["f64", "f32ir", "f32ru"])
 def test_ch_mass_energy_gpu(native, prec):
-    precision = native.SC_PREC_F64 if prec == "f64" else native.SC_PREC_F32_IR
+    precision = _PREC[prec](native)
     N = 128
     h = 1.0 / N
     eps, dt, Sst = 4 * h, 0.1 * h * h, 2.0

@@ -87,8 +87,8 @@ def test_request_larger_than_budget_is_rejected():
 
 def test_cancel_queued_and_unknown():
     op = _op()
-    # Budget for nothing resident keeps later requests queued behind a
-    # rejected head only until it is retired; use one slot and a long head.
+    # One slot and a long-running head keep the later requests queued while
+    # one of them is cancelled.
     srv = nat.Server(fake_device=True, max_slots=1)
     try:
         big = srv.submit_bvp(op, 1.0 / 1025, np.ones((1023, 1023)))
@@ -130,3 +130,19 @@ def test_destroy_with_queued_requests_returns():
     t = time.time()
     srv.close()
     assert time.time() - t < 10.0
+
+
+def test_precision_validation():
+    op = _op()
+    with pytest.raises(nat.ScError):
+        nat.Server(fake_device=True, precision=9)
+    srv = nat.Server(fake_device=True, max_slots=2)
+    try:
+        with pytest.raises(nat.ScError):
+            srv.submit_bvp(op, 1.0 / 33, np.ones((31, 31)), precision=7)
+        ids = [srv.submit_bvp(op, 1.0 / 33, np.ones((31, 31)), precision=p)
+               for p in (nat.SC_PREC_F64, nat.SC_PREC_F32_IR, nat.SC_PREC_F32_RU)]
+        res = _drain(srv, 3)
+        assert all(res[i]["status"] == nat.SC_OK for i in ids)
+    finally:
+        srv.close()
