@@ -9,6 +9,8 @@
 //   2D solve : CROSS 1,2  DIAMOND 2  CROSSBOX 4  BOX 1,2
 //   3D apply : CROSS 1,2  DIAMOND 2  BOX 1,2                (radius <= 2)
 //   3D solve : CROSS 1    DIAMOND 2  BOX 1
+//   3D mirror-symmetric (wave-private DMA ring): apply CROSS 1,2 DIAMOND 2
+//              BOX 1; solve CROSS 1 DIAMOND 2 BOX 1
 //   CH right-hand side (the Laplacian): CROSS 1,2
 #include "launch.hpp"
 
@@ -63,6 +65,19 @@ namespace sc {
   SC_CASE3(T, KIND, PER, PAT_BOX, 1)
 
 #define SC_KEY (L.ks->dim == 2 ? SC_KEY2(L.ks->pat, L.ks->R, L.ks->sym ? 1 : 0) : (L.ks->pat * 16 + L.ks->R))
+
+// symmetric 3D sweep (mirror-symmetric stencils only)
+#define SC_CASE3S(T, KIND, PER, P, RR) \
+  case P * 16 + RR: return run3s<T, KIND, P, RR, PER>(L, st);
+#define SC_APPLY3S_SET(T, PER)               \
+  SC_CASE3S(T, K_APPLY, PER, PAT_CROSS, 1)   \
+  SC_CASE3S(T, K_APPLY, PER, PAT_CROSS, 2)   \
+  SC_CASE3S(T, K_APPLY, PER, PAT_DIAMOND, 2) \
+  SC_CASE3S(T, K_APPLY, PER, PAT_BOX, 1)
+#define SC_SOLVE3S_SET(T, KIND, PER)          \
+  SC_CASE3S(T, KIND, PER, PAT_CROSS, 1)       \
+  SC_CASE3S(T, KIND, PER, PAT_DIAMOND, 2)     \
+  SC_CASE3S(T, KIND, PER, PAT_BOX, 1)
 
 #if SC_PART == 0
 hipError_t part_apply2d_f64(const SweepLaunch& L, hipStream_t st) {
@@ -165,6 +180,56 @@ hipError_t part_solve3d_f32(const SweepLaunch& L, hipStream_t st) {
     switch (SC_KEY) { SC_SOLVE3D_SET(float, K_CGDIR, true) default: break; }
   } else {
     switch (SC_KEY) { SC_SOLVE3D_SET(float, K_CGDIR, false) default: break; }
+  }
+  return hipErrorInvalidValue;
+}
+#elif SC_PART == 8
+hipError_t part_apply3s(const SweepLaunch& L, hipStream_t st) {
+  if (L.kind != K_APPLY || !L.ks->sym) return hipErrorInvalidValue;
+  if (L.dtype == SC_F64) {
+    if (L.periodic) { switch (SC_KEY) { SC_APPLY3S_SET(double, true) default: break; } }
+    else { switch (SC_KEY) { SC_APPLY3S_SET(double, false) default: break; } }
+  } else {
+    if (L.periodic) { switch (SC_KEY) { SC_APPLY3S_SET(float, true) default: break; } }
+    else { switch (SC_KEY) { SC_APPLY3S_SET(float, false) default: break; } }
+  }
+  return hipErrorInvalidValue;
+}
+#elif SC_PART == 9
+hipError_t part_solve3s_f64(const SweepLaunch& L, hipStream_t st) {
+  if (!L.ks->sym) return hipErrorInvalidValue;
+  switch (L.kind) {
+    case K_CGDIR:
+      if (L.periodic) { switch (SC_KEY) { SC_SOLVE3S_SET(double, K_CGDIR, true) default: break; } }
+      else { switch (SC_KEY) { SC_SOLVE3S_SET(double, K_CGDIR, false) default: break; } }
+      break;
+    case K_RESID:
+      if (L.periodic) { switch (SC_KEY) { SC_SOLVE3S_SET(double, K_RESID, true) default: break; } }
+      else { switch (SC_KEY) { SC_SOLVE3S_SET(double, K_RESID, false) default: break; } }
+      break;
+    case K_BVPRHS:
+      if (!L.periodic) { switch (SC_KEY) { SC_SOLVE3S_SET(double, K_BVPRHS, false) default: break; } }
+      break;
+    case K_CHRHS:
+      if (L.periodic) {
+        switch (SC_KEY) {
+          SC_CASE3S(double, K_CHRHS, true, PAT_CROSS, 1)
+          SC_CASE3S(double, K_CHRHS, true, PAT_CROSS, 2)
+          default: break;
+        }
+      }
+      break;
+    default: break;
+  }
+  return hipErrorInvalidValue;
+}
+#elif SC_PART == 10
+hipError_t part_solve3s_f32(const SweepLaunch& L, hipStream_t st) {
+  if (L.kind != K_CGDIR || !L.ks->sym) return hipErrorInvalidValue;
+  if (L.periodic) {
+    switch (SC_KEY) { SC_SOLVE3S_SET(float, K_CGDIR, true) default: break; }
+  } else {
+    switch (SC_KEY) { SC_SOLVE3S_SET(float, K_CGDIR, false) default: break; }
   }
   return hipErrorInvalidValue;
 }

@@ -92,6 +92,11 @@ struct SweepLaunch {
   int flag = 0;
   bool vec_store = false;
   bool in_aligned = false;  // in / in2 / aux rows start on 16-byte boundaries
+  // Ring mode: columns [in_xlo, in_xhi) of every in / in2 row and [0, aux_xhi)
+  // of every aux row may be read (values outside the ring feed no output).
+  // Unset (x_range false): the ring itself, [-R, n0 + R) and [0, n0).
+  bool x_range = false;
+  int64_t in_xlo = 0, in_xhi = 0, aux_xhi = 0;
 };
 
 // Number of blocks (= partial-sum slots) the sweep will launch.
@@ -109,6 +114,9 @@ hipError_t part_solve2d_f32(const SweepLaunch& L, hipStream_t st);
 hipError_t part_apply3d(const SweepLaunch& L, hipStream_t st);
 hipError_t part_solve3d_f64(const SweepLaunch& L, hipStream_t st);
 hipError_t part_solve3d_f32(const SweepLaunch& L, hipStream_t st);
+hipError_t part_apply3s(const SweepLaunch& L, hipStream_t st);
+hipError_t part_solve3s_f64(const SweepLaunch& L, hipStream_t st);
+hipError_t part_solve3s_f32(const SweepLaunch& L, hipStream_t st);
 
 // Vector layout of solver workspace: pointers address the interior
 // (0,0,0) element, rows of `pitch` elements, planes of `zpitch`.
@@ -116,6 +124,8 @@ struct Layout {
   int64_t pitch = 0;
   int64_t zpitch = 0;
   int halo = 0;
+  int64_t xhi = 0;  // columns [-halo_x, xhi) of every row lie inside the allocation
+  int halo_x = 0;
 };
 
 constexpr int kElemBlocks = 1024;  // blocks of the element-wise kernels

@@ -5,6 +5,7 @@
 
 #include "internal.hpp"
 #include "sweep3d.hpp"
+#include "sweep3s.hpp"
 
 namespace sc {
 
@@ -57,6 +58,10 @@ SweepArgs<T> make_args(const SweepLaunch& L) {
   a.vec_store = L.vec_store ? 1 : 0;
   a.in_aligned = L.in_aligned ? 1 : 0;
   a.alt = 0;
+  const int R = L.ks ? L.ks->R : 0;
+  a.xlo = L.x_range ? L.in_xlo : -R;
+  a.xhi = L.x_range ? L.in_xhi : L.n[0] + R;
+  a.axhi = L.x_range ? L.aux_xhi : L.n[0];
   return a;
 }
 
@@ -95,6 +100,59 @@ inline void geom3d(const SweepLaunch& L, int R, SweepArgs<T>& a, int* blocks) {
   *blocks = a.tiles_a * a.tiles_b;
 }
 
+// Tile rows and plane look-ahead of the symmetric 3D sweep, by kind: the
+// direction sweep holds two input rings, so it takes taller tiles (less
+// y-halo re-reading per output) and a shallower look-ahead.
+template <int KIND>
+constexpr int tile3s_rows() { return KIND == K_CGDIR ? 4 : 2; }
+template <int KIND>
+constexpr int lookahead3s() { return KIND == K_CGDIR ? 2 : 3; }
+
+// Geometry of the symmetric 3D sweep. Each wave streams a z chunk of one
+// x-y tile; the chunk length is chosen so that all tiles are resident at
+// once (`capacity` = waves the device holds for this kernel), which avoids a
+// partial last round of waves, but no shorter than max(2R, 4) planes.
+template <typename T, int TY>
+inline void geom3s(const SweepLaunch& L, int R, SweepArgs<T>& a, int* blocks, int64_t capacity) {
+  constexpr int VPL = 16 / (int)sizeof(T);
+  constexpr int64_t TXW = 64 * VPL;
+  const int RA = ((R + VPL - 1) / VPL) * VPL;
+  const int64_t tx = (L.n[0] + TXW - 1) / TXW;
+  const int64_t ty = (L.n[1] + TY - 1) / TY;
+  const int64_t txy = tx * ty;
+  int64_t chunks = capacity / txy;
+  if (chunks < 1) chunks = 1;
+  int64_t tz = (L.n[2] + chunks - 1) / chunks;
+  const int64_t lo = 2 * R > 4 ? 2 * R : 4;
+  if (const char* e = std::getenv("SCOMP_TZ3S")) {
+    const int v = std::atoi(e);
+    if (v > 0) tz = v;
+  }
+  if (tz < lo) tz = lo;
+  if (tz > L.n[2]) tz = L.n[2];
+  a.tiles_x2 = (int)tx;
+  a.tiles_a = (int)txy;
+  a.ty = (int)tz;
+  a.tiles_b = (int)((L.n[2] + tz - 1) / tz);
+  // a single wrap (wrap_once) covers every index the tile touches only when
+  // the grid is wider than the tile plus its halo
+  a.small = (L.n[0] <= TXW + RA || L.n[1] <= TY + R || L.n[2] <= R) ? 1 : 0;
+  *blocks = a.tiles_a * a.tiles_b;
+}
+// Upper bound on the waves a device holds (partial-sum sizing).
+constexpr int64_t kMaxResidentWaves = 8192;
+
+// Class weights (|dx|, |dy|, |dz|) of a 3D mirror-symmetric stencil.
+template <typename T, int PAT, int R>
+Taps<T, sym3_nweights(R)> make_sym3_taps(const KStencil& ks) {
+  Taps<T, sym3_nweights(R)> t{};
+  for (int az = 0; az <= R; ++az)
+    for (int b = 0; b <= R; ++b)
+      for (int d = 0; d <= R; ++d)
+        if (in_pattern(PAT, R, d, b, az)) t.w[sym3_index(R, d, b, az)] = (T)ks.w[tap_index(PAT, R, 3, d, b, az)];
+  return t;
+}
+
 // Class weights (|dx|, |dy|) of a mirror-symmetric stencil.
 template <typename T, int PAT, int R>
 Taps<T, sym_num_classes(PAT, R)> make_sym_taps(const KStencil& ks) {
@@ -131,6 +189,29 @@ hipError_t run3d(const SweepLaunch& L, hipStream_t st) {
   const auto taps = make_taps<T, num_taps(PAT, R, 3)>(*L.ks);
   hipLaunchKernelGGL((sweep3d_kernel<T, KIND, PAT, R, PER, NT>), dim3(blocks), dim3(NT), 0, st, a,
                      taps);
+  return hipGetLastError();
+}
+
+template <typename T, int KIND, int PAT, int R, bool PER>
+hipError_t run3s(const SweepLaunch& L, hipStream_t st) {
+  constexpr int TY = tile3s_rows<KIND>();
+  constexpr int D = lookahead3s<KIND>();
+  const auto kern = sweep3s_kernel<T, KIND, PAT, R, PER, TY, D>;
+  // waves of this kernel the device holds at once (LDS and registers)
+  static const int64_t capacity = [&] {
+    int per_cu = 0, cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0) != hipSuccess || per_cu < 1 || cus < 1)
+      return (int64_t)1024;
+    const int64_t c = (int64_t)per_cu * cus;
+    return c < kMaxResidentWaves ? c : kMaxResidentWaves;
+  }();
+  SweepArgs<T> a = make_args<T>(L);
+  int blocks = 0;
+  geom3s<T, TY>(L, R, a, &blocks, capacity);
+  const auto taps = make_sym3_taps<T, PAT, R>(*L.ks);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), 0, st, a, taps);
   return hipGetLastError();
 }
 

@@ -16,13 +16,19 @@ int sweep_blocks(const SweepLaunch& L) {
       geom2d<float>(L, R, a, &blocks);
     }
   } else {
+    // the symmetric and the general 3D sweeps tile differently: size the
+    // partial sums for whichever launches
+    int b2 = 0;
     if (L.dtype == SC_F64) {
       SweepArgs<double> a{};
       geom3d<double, 256>(L, R, a, &blocks);
+      geom3s<double, 2>(L, R, a, &b2, kMaxResidentWaves);
     } else {
       SweepArgs<float> a{};
       geom3d<float, 256>(L, R, a, &blocks);
+      geom3s<float, 2>(L, R, a, &b2, kMaxResidentWaves);
     }
+    blocks = blocks > b2 ? blocks : b2;
   }
   return blocks;
 }
@@ -36,6 +42,15 @@ hipError_t route(const SweepLaunch& L, hipStream_t st) {
     return L.periodic ? part_solve2d_f64_periodic(L, st) : part_solve2d_f64_ring(L, st);
   }
   if (L.ks->dim == 3) {
+    static const bool no3s = std::getenv("SCOMP_NO3S") != nullptr;  // A/B switch to the general kernel
+    if (L.ks->sym && !no3s) {
+      hipError_t e;
+      if (L.kind == K_APPLY)
+        e = part_apply3s(L, st);
+      else
+        e = L.dtype == SC_F32 ? part_solve3s_f32(L, st) : part_solve3s_f64(L, st);
+      if (e != hipErrorInvalidValue) return e;
+    }
     if (L.kind == K_APPLY) return part_apply3d(L, st);
     if (L.dtype == SC_F32) return part_solve3d_f32(L, st);
     return part_solve3d_f64(L, st);

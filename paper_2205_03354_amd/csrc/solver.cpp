@@ -92,13 +92,23 @@ sc_status launch(SweepLaunch L, hipStream_t st) {
 }
 
 
+// Rows are padded so that the sweeps' 16-byte chunk DMAs of a strip
+// (64 x 16 bytes plus halo chunks) stay inside the row even where the strip
+// runs past the last column: the padding is zero and feeds no output.
 Layout make_layout(int dim, const int64_t* n, int halo, int dtype) {
   const int64_t es = (int64_t)esize(dtype);
   const int64_t align_e = 256 / es;
+  const int64_t vpl = 16 / es;
+  const int64_t txw = 64 * vpl;
+  const int64_t ra = halo ? (halo + vpl - 1) / vpl * vpl : 0;
+  int64_t width = n[0] + 2 * halo;
+  if (halo) width = std::max<int64_t>(width, halo + (n[0] + txw - 1) / txw * txw + ra);
   Layout lay;
-  lay.pitch = (n[0] + 2 * halo + align_e - 1) / align_e * align_e;
+  lay.pitch = (width + align_e - 1) / align_e * align_e;
   lay.zpitch = lay.pitch * (n[1] + 2 * halo);
   lay.halo = halo;
+  lay.halo_x = (int)ra;
+  lay.xhi = lay.pitch - halo;
   (void)dim;
   return lay;
 }
@@ -247,6 +257,13 @@ sc_status SolveTask::sweep(int kind, int dtype, const KStencil& ks, const void* 
     L.in = in;
     L.pin = lin->pitch;
     L.zin = lin->zpitch;
+  }
+  // workspace vectors carry padded rows (see make_layout); views do not
+  if (!periodic_ && !in_view && !aux_view) {
+    L.x_range = true;
+    L.in_xlo = -lin->halo_x;
+    L.in_xhi = lin->xhi;
+    L.aux_xhi = lout.xhi;
   }
   L.in2 = in2;
   L.pin2 = lout.pitch;

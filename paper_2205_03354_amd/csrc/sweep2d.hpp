@@ -57,6 +57,8 @@ struct SweepArgs {
   int vec_store;          // outputs 16-byte aligned for the vector store
   int in_aligned;         // 2D: inputs (in, in2, aux) have 16-byte aligned rows
   int alt;                // 2D: alternate the streaming direction by tile row
+  int64_t xlo, xhi;       // ring mode: columns [xlo, xhi) of every in / in2 row are readable
+  int64_t axhi;           // columns [0, axhi) of every aux row are readable
   DevScalars* scal;
   double* partials;
   double c0, c1, c2;      // K_CHRHS: dt, 1+S; K_BVPRHS/K_CHRHS: c2 = tol^2
@@ -192,8 +194,8 @@ __global__ void __launch_bounds__(64)
   // chunk DMA needs 16-byte aligned rows, no periodic seam inside the strip
   // and (ring mode) every loaded column inside the stored ring
   const bool fast = a.in_aligned && !a.small &&
-                    (PER ? (lo >= 0 && lo + W <= a.n0) : (lo >= -R && lo + W <= a.n0 + R)) &&
-                    (!AUX || x0 + TXW <= a.n0);
+                    (PER ? (lo >= 0 && lo + W <= a.n0) : (lo >= a.xlo && lo + W <= a.xhi)) &&
+                    (!AUX || x0 + TXW <= a.axhi);
   const bool rev = SYM && a.alt && (syi & 1);
 
   // input row index q (0 .. NR-1, streaming order) -> grid row

@@ -169,6 +169,35 @@ def test_apply3d_f64(native, name, size):
     assert scaled_error(got, ref, st, xh, capi.HALO, r) <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["lap7", "bilap25", "box1"])
+@pytest.mark.parametrize("size", [(256, 13, 37), (128, 128, 40), (130, 9, 21)])
+def test_apply3d_f64_multi_tile(native, name, size):
+    # Mirror-symmetric 3D stencils take the wave-per-tile DMA-ring sweep:
+    # several x strips, a ragged last row tile and several ragged z chunks;
+    # (130, ...) has a partial last strip.
+    st = STENCILS_3D[name]()
+    n0, n1, n2 = size
+    x = S.uniform_field((n2, n1, n0), seed=n0 + 3 * n1 + 7 * n2)
+    got = _run(native, st, x, native.SC_BC_PERIODIC, 0, torch.float64)
+    ref = capi.apply(st, x, capi.PERIODIC)
+    assert scaled_error(got, ref, st, x, capi.PERIODIC) <= 1e-12
+    r = st.radius()
+    xh = padded(x, r, fill_seed=5)
+    got = _run(native, st, xh, native.SC_BC_HALO, r, torch.float64)
+    ref = capi.apply(st, xh, capi.HALO, r)
+    assert scaled_error(got, ref, st, xh, capi.HALO, r) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["lap7", "bilap25"])
+def test_apply3d_integer_bit_exact_f32_multi_tile(native, name):
+    st = STENCILS_3D[name]()
+    nums, den = st.integer_form()
+    sti = R.RStencil(3, 0, dict(nums))
+    x = S.integer_field((23, 18, 512), seed=6, lo=-32, hi=32)
+    got = _run(native, sti, x, native.SC_BC_PERIODIC, 0, torch.float32)
+    assert np.array_equal(got, capi.apply(sti, x, capi.PERIODIC))
+
+
 @pytest.mark.parametrize("name", list(STENCILS_3D))
 def test_apply3d_integer_bit_exact_f32(native, name):
     st = STENCILS_3D[name]()
