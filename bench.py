@@ -134,23 +134,53 @@ def ch_bench(native, torch, steps: int):
     from paper_2205_03354_amd import stencils
 
     dev = torch.device("cuda:0")
-    N = 1024
-    h = 1.0 / N
-    out = {}
-    L = stencils.laplacian(2)
-    for name, prec in (("f64", native.SC_PREC_F64), ("f32_ir", native.SC_PREC_F32_IR),
-                       ("f32_ru", native.SC_PREC_F32_RU)):
-        u = torch.from_numpy(S.zero_mean_uniform((N, N), seed=0)).to(dev)
-        native.ch_step(L, u, h, 4 * h, 0.1 * h * h, 2.0, precision=prec)  # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        its = 0
-        for _ in range(steps):
-            st = native.ch_step(L, u, h, 4 * h, 0.1 * h * h, 2.0, precision=prec)
-            its += st.iterations
-        dt = (time.perf_counter() - t0) / steps
-        out[name] = {"ms_per_step": round(dt * 1e3, 3), "iterations_per_step": its / steps}
-    return {"workload": "Cahn-Hilliard step, 1024^2 periodic, eps=4h, dt=0.1h^2, S=2, to 1e-10", **out}
+    res = {"workload": "Cahn-Hilliard steps, periodic, eps=4h, dt=0.1h^2, S=2, u0 ~ U[-0.05,0.05] minus its "
+                       "mean, each step's solve to a 1e-10 true relative residual"}
+    for dim, N in ((2, 1024), (3, 256)):
+        h = 1.0 / N
+        L = stencils.laplacian(dim)
+        out = {}
+        for name, prec in (("f64", native.SC_PREC_F64), ("f32_ir", native.SC_PREC_F32_IR),
+                           ("f32_ru", native.SC_PREC_F32_RU)):
+            u = torch.from_numpy(S.zero_mean_uniform((N,) * dim, seed=0)).to(dev)
+            native.ch_step(L, u, h, 4 * h, 0.1 * h * h, 2.0, precision=prec)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its = 0
+            for _ in range(steps):
+                st = native.ch_step(L, u, h, 4 * h, 0.1 * h * h, 2.0, precision=prec)
+                its += st.iterations
+            dt = (time.perf_counter() - t0) / steps
+            out[name] = {"ms_per_step": round(dt * 1e3, 3), "iterations_per_step": its / steps}
+        res[f"{N}^{dim}"] = out
+    return res
+
+
+def bvp3d_bench(native, torch):
+    """3D biharmonic BVPs (25-point 7-point-Laplacian composition), solves
+    to a 1e-10 true relative residual, FP64 and FP32 with reliable updates."""
+    import synthetic as S
+    from paper_2205_03354_amd import stencils
+
+    dev = torch.device("cuda:0")
+    op = stencils.biharmonic(3)
+    res = {"workload": "3D biharmonic BVP, sin(pi x) sin(pi y) sin(pi z), n^3 unknowns, 2-ring from the exact u"}
+    for n in (63, 127):
+        bvp = S.biharmonic_bvp(3, n)
+        f = torch.from_numpy(bvp.f).to(dev)
+        g = torch.from_numpy(bvp.g).to(dev)
+        out = {}
+        for name, prec in (("f64", native.SC_PREC_F64), ("f32_ru", native.SC_PREC_F32_RU)):
+            u = torch.zeros_like(f)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = native.solve_biharmonic(op, bvp.h, f, u, g=g, g_halo=bvp.halo, tol=1e-10, precision=prec)
+            dt = time.perf_counter() - t0
+            err = float((u.cpu() - torch.from_numpy(bvp.u)).abs().max())
+            out[name] = {"ms": round(dt * 1e3, 2), "iterations": st.iterations, "rel_residual": st.rel_residual,
+                         "max_error_vs_exact": err}
+        res[f"{n}^3"] = out
+    return res
 
 
 def _pct(vals, q):
@@ -298,7 +328,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-extras", action="store_true", help="only the timed apply (for profiling)")
-    ap.add_argument("--extras", default="solves,ch,serve,cpu",
+    ap.add_argument("--extras", default="solves,ch,bvp3d,serve,cpu",
                     help="comma-separated extras to run after the timed apply")
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--copy-probe", action="store_true",
@@ -393,13 +423,21 @@ def main():
                      "traffic": traffic},
     }
     extras = set() if args.no_extras else set(x for x in args.extras.split(",") if x)
+    if extras:
+        print(f"[bench] apply {value:.0f} GB/s; extras: {sorted(extras)}", file=sys.stderr, flush=True)
     if "solves" in extras:
+        print("[bench] solves", file=sys.stderr, flush=True)
         result["solves"] = solver_bench(native, torch, reps=20)
     if "ch" in extras:
-        result["ch"] = ch_bench(native, torch, steps=5)
+        print("[bench] ch", file=sys.stderr, flush=True)
+        result["ch"] = ch_bench(native, torch, steps=3)
+    if "bvp3d" in extras:
+        print("[bench] bvp3d", file=sys.stderr, flush=True)
+        result["bvp3d"] = bvp3d_bench(native, torch)
     if "serve" in extras:
         result["serve"] = serve_bench(native, torch, args.serve_requests)
     if "cpu" in extras:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
 

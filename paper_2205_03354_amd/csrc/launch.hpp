@@ -13,12 +13,14 @@ namespace sc {
 // of the waves one MI355X keeps resident (16 per CU), so that the tiles in
 // flight at any moment cover a compact band of rows, without making tiles so
 // short that the 2R halo rows dominate.
-inline int tile_rows_2d(int64_t n1, int64_t strips, int R) {
+inline int tile_rows_2d(int64_t n1, int64_t strips, int R, int64_t capacity) {
   if (const char* e = std::getenv("SCOMP_TY2D")) {
     const int v = std::atoi(e);
     if (v > 0) return v;
   }
-  int64_t ty = (n1 * strips + 8191) / 8192;
+  // as many tiles as the device holds waves of the kernel at once (one
+  // round of waves), but tiles of at least max(4R, 12) rows
+  int64_t ty = (n1 * strips + capacity - 1) / capacity;
   const int64_t lo = 4 * R > 12 ? 4 * R : 12;
   if (ty < lo) ty = lo;
   if (ty > n1) ty = n1;
@@ -74,10 +76,10 @@ Taps<T, N> make_taps(const KStencil& ks) {
 
 // Geometry of a 2D launch: one wave per tile, strips of 64 * VPL columns.
 template <typename T>
-inline void geom2d(const SweepLaunch& L, int R, SweepArgs<T>& a, int* blocks) {
+inline void geom2d(const SweepLaunch& L, int R, SweepArgs<T>& a, int* blocks, int64_t capacity) {
   const int64_t TX = strip_width_2d<T>();
   const int64_t strips = (L.n[0] + TX - 1) / TX;
-  a.ty = tile_rows_2d(L.n[1], strips, R);
+  a.ty = tile_rows_2d(L.n[1], strips, R, capacity);
   const int64_t ty = (L.n[1] + a.ty - 1) / a.ty;
   a.tiles_a = (int)strips;
   a.tiles_b = (int)ty;
@@ -163,20 +165,34 @@ Taps<T, sym_num_classes(PAT, R)> make_sym_taps(const KStencil& ks) {
   return t;
 }
 
+// Waves of kernel `kern` (64-thread blocks) the device holds at once.
+template <typename K>
+int64_t resident_waves(K kern) {
+  int per_cu = 0, cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0) != hipSuccess || per_cu < 1 || cus < 1)
+    return 4096;
+  const int64_t c = (int64_t)per_cu * cus;
+  return c < kMaxResidentWaves ? c : kMaxResidentWaves;
+}
+
 template <typename T, int KIND, int PAT, int R, bool PER, bool SYM>
 hipError_t run2d(const SweepLaunch& L, hipStream_t st) {
+  const auto kern = sweep2d_kernel<T, KIND, PAT, R, PER, SYM>;
+  static const int64_t capacity = resident_waves(kern);
   SweepArgs<T> a = make_args<T>(L);
   int blocks = 0;
-  geom2d<T>(L, R, a, &blocks);
+  geom2d<T>(L, R, a, &blocks, capacity);
   a.alt = SYM ? 1 : 0;
   if (const char* e = std::getenv("SCOMP_NOALT"))
     if (e[0] == '1') a.alt = 0;
   if constexpr (SYM) {
     const auto taps = make_sym_taps<T, PAT, R>(*L.ks);
-    hipLaunchKernelGGL((sweep2d_kernel<T, KIND, PAT, R, PER, true>), dim3(blocks), dim3(64), 0, st, a, taps);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), 0, st, a, taps);
   } else {
     const auto taps = make_taps<T, num_taps(PAT, R, 2)>(*L.ks);
-    hipLaunchKernelGGL((sweep2d_kernel<T, KIND, PAT, R, PER, false>), dim3(blocks), dim3(64), 0, st, a, taps);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), 0, st, a, taps);
   }
   return hipGetLastError();
 }
@@ -197,16 +213,7 @@ hipError_t run3s(const SweepLaunch& L, hipStream_t st) {
   constexpr int TY = tile3s_rows<KIND>();
   constexpr int D = lookahead3s<KIND>();
   const auto kern = sweep3s_kernel<T, KIND, PAT, R, PER, TY, D>;
-  // waves of this kernel the device holds at once (LDS and registers)
-  static const int64_t capacity = [&] {
-    int per_cu = 0, cus = 0, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0) != hipSuccess || per_cu < 1 || cus < 1)
-      return (int64_t)1024;
-    const int64_t c = (int64_t)per_cu * cus;
-    return c < kMaxResidentWaves ? c : kMaxResidentWaves;
-  }();
+  static const int64_t capacity = resident_waves(kern);  // LDS and registers
   SweepArgs<T> a = make_args<T>(L);
   int blocks = 0;
   geom3s<T, TY>(L, R, a, &blocks, capacity);

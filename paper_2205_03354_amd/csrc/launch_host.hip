@@ -10,10 +10,10 @@ int sweep_blocks(const SweepLaunch& L) {
   if (L.ks->dim == 2) {
     if (L.dtype == SC_F64) {
       SweepArgs<double> a{};
-      geom2d<double>(L, R, a, &blocks);
+      geom2d<double>(L, R, a, &blocks, kMaxResidentWaves);
     } else {
       SweepArgs<float> a{};
-      geom2d<float>(L, R, a, &blocks);
+      geom2d<float>(L, R, a, &blocks, kMaxResidentWaves);
     }
   } else {
     // the symmetric and the general 3D sweeps tile differently: size the
