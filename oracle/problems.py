@@ -17,6 +17,9 @@ statement of the problem:
 * ``ch_energy`` / ``mass``: the discrete free energy of Sec. 4.1 for the
   double well (u^2-1)^2/4 with gradient coefficient eps^2 (forward
   differences), and h^d sum u.
+* ``flux_terms`` / ``varcoef_apply``: a composition with a varying
+  coefficient between its factors (Sec. 2.2.3): y = sum_t B_t(M * A_t(x)),
+  e.g. div(M grad(Lap f)) with A_a = D1_a o Lap and B_a = D1_a.
 """
 
 from __future__ import annotations
@@ -91,3 +94,43 @@ def ch_energy(u: np.ndarray, h: float, eps: float) -> float:
         d = (np.roll(u, -1, axis=ax) - u) / h
         grad = grad + d * d
     return float(h ** u.ndim * np.sum(bulk + 0.5 * eps * eps * grad))
+
+
+# -- variable-coefficient composition ----------------------------------------
+
+def flux_terms(dim: int, inner: R.RStencil):
+    """The terms (A_a, B_a) of div(M grad(inner f)) with central first
+    derivatives: A_a = D1_a o inner, B_a = D1_a (Sec. 2.2.3: the inner part is
+    composed first, scaled pointwise by the mobility M, and the result is
+    composed with the outer first derivative)."""
+    terms = []
+    for a in range(dim):
+        d1 = R.embed(R.central_first(), a, dim)
+        terms.append((R.compose(d1, inner), d1))
+    return terms
+
+
+def varcoef_apply(terms, M: np.ndarray, x: np.ndarray, mode: int, halo: int = 0, h: float = 1.0) -> np.ndarray:
+    """y = sum_t B_t(M * A_t(x)), by definition: each inner stencil applied to
+    x, the result multiplied pointwise by M, the outer stencil applied to that.
+
+    PERIODIC: x and M have the grid's shape. HALO: x carries a ring of width
+    halo >= rA + rB (rA, rB the largest inner and outer radii) and M a ring of
+    width halo - rA around the grid, so that M * A_t(x) is defined on the
+    grid plus the ring the outer stencils read."""
+    y = None
+    if mode == capi.PERIODIC:
+        for A, B in terms:
+            w = M * capi.apply(A, x, capi.PERIODIC, 0, h)
+            t = capi.apply(B, w, capi.PERIODIC, 0, h)
+            y = t if y is None else y + t
+        return y
+    rA = max(A.radius() for A, _ in terms)
+    rB = halo - rA
+    if rB < max(B.radius() for _, B in terms):
+        raise ValueError("halo must cover the inner plus the outer radius")
+    for A, B in terms:
+        w = M * capi.apply(A, x, capi.HALO, rA, h)  # on the grid plus a ring of width rB
+        t = capi.apply(B, w, capi.HALO, rB, h)
+        y = t if y is None else y + t
+    return y
