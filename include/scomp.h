@@ -167,7 +167,7 @@ void sc_stencil_free(sc_stencil* s);
  * applying a stencil, Sec. 2.1; for a composed stencil the taps are those of
  * eq. (C=B(A)), so one pass replaces the two sequential passes of the
  * factors). `in` and `out` must share dim, n and dtype, and must not
- * overlap in memory. In SC_BC_HALO mode in->halo >= radius(s). Only the
+ * overlap in memory. In SC_BC_HALO mode in->halo >= max(1, radius(s)). Only the
  * interior of `out` is written; its ring is left untouched.
  * Supported: dim 2 with radius <= 4, dim 3 with radius <= 2 (any pattern
  * inside those boxes). Asynchronous on `stream`.
@@ -175,6 +175,25 @@ void sc_stencil_free(sc_stencil* s);
  */
 sc_status sc_apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_grid* out,
                             sc_bc bc, sc_stream_t stream);
+
+/*
+ * Composition with a varying coefficient between the factors (Sec. 2.2.3,
+ * where a spatially varying mobility M sits between an outer first
+ * derivative and the composed inner part, as in d_x(M d_x(d_xx f))):
+ *     out = sum_{t < nterms} outer[t]( mob * inner[t](in) ),
+ * with `*` the pointwise product. For div(M grad(L f)) the terms are
+ * inner[a] = D1_a o L and outer[a] = D1_a, a over the axes.
+ * `mob` (the coefficient), `in` and `out` share dim, n and dtype; out must
+ * not overlap them. SC_BC_PERIODIC: indices wrap. SC_BC_HALO: in->halo >=
+ * rA + rB and mob->halo >= rB (rA, rB the largest inner and outer radii),
+ * since mob * inner(in) is needed on the grid plus the ring the outer
+ * stencils read. 1 <= nterms <= 16. Each term is two sweeps through a
+ * library workspace, so the call returns after its work on `stream` has
+ * completed. Errors: SC_EINVAL, SC_EUNSUPPORTED, SC_ENOMEM, SC_EDEVICE.
+ */
+sc_status sc_apply_varcoef(int32_t nterms, const sc_stencil* const* inner, const sc_stencil* const* outer,
+                           double h, const sc_grid* mob, const sc_grid* in, sc_grid* out, sc_bc bc,
+                           sc_stream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Krylov solves
@@ -216,7 +235,7 @@ void sc_solve_opts_default(sc_solve_opts* opts);
  * composed Laplacian), to ||b - A0 x|| <= tol ||b|| checked on the true
  * residual.
  *   f  FP64 grid, the forcing at the unknowns (ring ignored).
- *   g  FP64 grid with halo >= radius(op) holding the ring values (interior
+ *   g  FP64 grid with halo >= max(1, radius(op)) holding the ring values (interior
  *      ignored), or NULL for a zero ring.
  *   u  FP64 grid: initial guess at the unknowns on entry, solution on
  *      return; its ring is not touched.
@@ -294,8 +313,9 @@ typedef struct sc_server_opts {
  * at submit (the caller may reuse them at once); u_out must stay valid until
  * the request's result has been polled.
  *   SC_REQ_BVP:     op = composed operator; f = forcing on the n unknowns;
- *                   g = ring values on the (n + 2 radius) box or NULL (zero
- *                   ring); u0 = initial guess or NULL (zero).
+ *                   g = ring values on the (n + 2 r) box, r = max(1,
+ *                   radius(op)), or NULL (zero ring); u0 = initial guess
+ *                   or NULL (zero).
  *   SC_REQ_CH_STEP: op = the Laplacian; u0 = u^n (periodic); ch = step
  *                   parameters; f, g unused.
  *   precision       sc_precision for this request, or -1 for the server's.

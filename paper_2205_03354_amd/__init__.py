@@ -20,6 +20,7 @@ from ._native import (  # noqa: F401
     SolveStats,
     Stencil,
     apply_composed,
+    apply_varcoef,
     ch_step,
     compose_stencil,
     grid_diagnostics,

@@ -25,7 +25,7 @@ SC_PREC_F64, SC_PREC_F32_IR, SC_PREC_F32_RU = 0, 1, 2
 
 EXPORTED = (
     "sc_stencil_create", "sc_compose_stencil", "sc_stencil_lincomb", "sc_stencil_get",
-    "sc_stencil_radius", "sc_stencil_free", "sc_apply_composed", "sc_solve_opts_default",
+    "sc_stencil_radius", "sc_stencil_free", "sc_apply_composed", "sc_apply_varcoef", "sc_solve_opts_default",
     "sc_solve_biharmonic", "sc_ch_step", "sc_grid_diagnostics", "sc_status_str",
     "sc_last_error", "sc_version", "sc_server_create", "sc_server_submit", "sc_server_poll",
     "sc_server_cancel", "sc_server_load", "sc_server_destroy",
@@ -90,6 +90,9 @@ def _load() -> ctypes.CDLL:
     L.sc_stencil_free.argtypes = [P]
     L.sc_stencil_free.restype = None
     L.sc_apply_composed.argtypes = [P, D, ctypes.POINTER(SCGrid), ctypes.POINTER(SCGrid), ctypes.c_int, P]
+    L.sc_apply_varcoef.argtypes = [I32, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), D,
+                                   ctypes.POINTER(SCGrid), ctypes.POINTER(SCGrid), ctypes.POINTER(SCGrid),
+                                   ctypes.c_int, P]
     L.sc_solve_opts_default.argtypes = [ctypes.POINTER(SCSolveOpts)]
     L.sc_solve_opts_default.restype = None
     L.sc_solve_biharmonic.argtypes = [P, D, ctypes.POINTER(SCGrid), ctypes.POINTER(SCGrid),
@@ -115,7 +118,8 @@ def _load() -> ctypes.CDLL:
     L.sc_version.argtypes = []
     L.sc_version.restype = ctypes.c_char_p
     for name in ("sc_stencil_create", "sc_compose_stencil", "sc_stencil_lincomb", "sc_stencil_get",
-                 "sc_apply_composed", "sc_solve_biharmonic", "sc_ch_step", "sc_grid_diagnostics"):
+                 "sc_apply_composed", "sc_apply_varcoef", "sc_solve_biharmonic", "sc_ch_step",
+                 "sc_grid_diagnostics"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -239,6 +243,19 @@ def apply_composed(st: Stencil, x, y, bc: int = SC_BC_PERIODIC, h: float = 1.0, 
     go = grid_of(y, halo if out_halo is None else out_halo)
     _check(lib.sc_apply_composed(st.handle, float(h), ctypes.byref(gi), ctypes.byref(go), int(bc),
                                  _stream(stream)))
+    return y
+
+
+def apply_varcoef(terms, mob, x, y, bc: int = SC_BC_PERIODIC, h: float = 1.0, halo: int = 0,
+                  mob_halo: int = 0, out_halo: int = 0, stream=None):
+    """y = sum_t outer_t(mob * inner_t(x)) for terms [(inner_t, outer_t)]
+    (see sc_apply_varcoef); returns after the work completes."""
+    n = len(terms)
+    inner = (ctypes.c_void_p * n)(*[t[0].handle.value for t in terms])
+    outer = (ctypes.c_void_p * n)(*[t[1].handle.value for t in terms])
+    gm, gi, go = grid_of(mob, mob_halo), grid_of(x, halo), grid_of(y, out_halo)
+    _check(lib.sc_apply_varcoef(n, inner, outer, float(h), ctypes.byref(gm), ctypes.byref(gi), ctypes.byref(go),
+                                int(bc), _stream(stream)))
     return y
 
 

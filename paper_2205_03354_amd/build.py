@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libscomp.so")
 ARCH = "gfx950"
-NPARTS = 11
+NPARTS = 13
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

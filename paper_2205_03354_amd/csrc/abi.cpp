@@ -97,6 +97,12 @@ sc_status sc_apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc
   SC_GUARD(return sc::apply_composed(s, h, in, out, bc, reinterpret_cast<hipStream_t>(stream));)
 }
 
+sc_status sc_apply_varcoef(int32_t nterms, const sc_stencil* const* inner, const sc_stencil* const* outer,
+                           double h, const sc_grid* mob, const sc_grid* in, sc_grid* out, sc_bc bc,
+                           sc_stream_t stream) {
+  SC_GUARD(return sc::apply_varcoef(nterms, inner, outer, h, mob, in, out, bc, reinterpret_cast<hipStream_t>(stream));)
+}
+
 void sc_solve_opts_default(sc_solve_opts* o) {
   if (!o) return;
   o->tol = 1e-10;

@@ -74,8 +74,19 @@ enum SweepKind : int {
   K_CGDIR = 1,    // p = r + beta p_old ; q = S p ; <p, q>  -> alpha
   K_RESID = 2,    // r = b - S x ; <r, r>                   -> rr_true (and a CG (re)start)
   K_BVPRHS = 3,   // b = f - S g_ring ; <b, b>              -> bb, rr_stop
-  K_CHRHS = 4     // rhs = u + dt S(u^3 - (1+S0) u) ; <rhs, rhs> -> bb, rr_stop
+  K_CHRHS = 4,    // rhs = u + dt S(u^3 - (1+S0) u) ; <rhs, rhs> -> bb, rr_stop
+  K_SCALE = 5,    // out = aux * S in   (pointwise coefficient after a stencil)
+  K_ACCUM = 6     // out = aux + S in   (aux may be out itself: accumulate)
 };
+
+// Kinds that reduce a dot product into DevScalars.
+__host__ __device__ constexpr bool kind_has_dot(int kind) {
+  return kind == K_CGDIR || kind == K_RESID || kind == K_BVPRHS || kind == K_CHRHS;
+}
+// Kinds that read `aux` at the output point.
+__host__ __device__ constexpr bool kind_reads_aux(int kind) {
+  return kind == K_RESID || kind == K_BVPRHS || kind == K_SCALE || kind == K_ACCUM;
+}
 
 // Weights of one pattern instance, passed by value as a kernel argument (so
 // they live in scalar registers / the kernel-argument segment, with no

@@ -12,6 +12,9 @@
 //   3D mirror-symmetric (wave-private DMA ring): apply CROSS 1,2 DIAMOND 2
 //              BOX 1; solve CROSS 1 DIAMOND 2 BOX 1
 //   CH right-hand side (the Laplacian): CROSS 1,2
+//   variable coefficient (generic kernels): 2D scale DIAMOND 2 CROSS 2 BOX
+//              2,3, accumulate CROSS 1,2 BOX 1; 3D scale DIAMOND 2 BOX 2,
+//              accumulate CROSS 1 BOX 1
 #include "launch.hpp"
 
 #ifndef SC_PART
@@ -230,6 +233,56 @@ hipError_t part_solve3s_f32(const SweepLaunch& L, hipStream_t st) {
     switch (SC_KEY) { SC_SOLVE3S_SET(float, K_CGDIR, true) default: break; }
   } else {
     switch (SC_KEY) { SC_SOLVE3S_SET(float, K_CGDIR, false) default: break; }
+  }
+  return hipErrorInvalidValue;
+}
+#elif SC_PART == 11
+// variable-coefficient applies: pointwise coefficient after the inner
+// stencil (first derivative of a Laplacian: DIAMOND 2 / BOX 2,3), and the
+// accumulating outer first derivative (CROSS 1, BOX 1)
+#define SC_VC2D_SET(T, PER)                        \
+  SC_CASE2(T, K_SCALE, PER, PAT_DIAMOND, 2, false) \
+  SC_CASE2(T, K_SCALE, PER, PAT_CROSS, 2, false)   \
+  SC_CASE2(T, K_SCALE, PER, PAT_BOX, 2, false)     \
+  SC_CASE2(T, K_SCALE, PER, PAT_BOX, 3, false)     \
+  SC_CASE2(T, K_SCALE, PER, PAT_CROSSBOX, 4, false) \
+  SC_CASE2(T, K_ACCUM, PER, PAT_CROSS, 1, false)   \
+  SC_CASE2(T, K_ACCUM, PER, PAT_CROSS, 2, false)   \
+  SC_CASE2(T, K_ACCUM, PER, PAT_BOX, 1, false)
+hipError_t part_varcoef2d(const SweepLaunch& L, hipStream_t st) {
+  if (L.ks->sym) return hipErrorInvalidValue;
+  const int key = SC_KEY2(L.ks->pat, L.ks->R, 0) + (L.kind == K_ACCUM ? 0x10000 : 0);
+#define SC_VKEY(P, RR, K) (SC_KEY2(P, RR, 0) + ((K) == K_ACCUM ? 0x10000 : 0))
+#undef SC_CASE2
+#define SC_CASE2(T, KIND, PER, P, RR, S) \
+  case SC_VKEY(P, RR, KIND): return run2d<T, KIND, P, RR, PER, S>(L, st);
+  if (L.dtype == SC_F64) {
+    if (L.periodic) { switch (key) { SC_VC2D_SET(double, true) default: break; } }
+    else { switch (key) { SC_VC2D_SET(double, false) default: break; } }
+  } else {
+    if (L.periodic) { switch (key) { SC_VC2D_SET(float, true) default: break; } }
+    else { switch (key) { SC_VC2D_SET(float, false) default: break; } }
+  }
+  return hipErrorInvalidValue;
+}
+#elif SC_PART == 12
+#define SC_VKEY3(P, RR, K) ((P) * 16 + (RR) + ((K) == K_ACCUM ? 0x10000 : 0))
+#define SC_VC3(T, KIND, PER, P, RR) \
+  case SC_VKEY3(P, RR, KIND): return run3d<T, KIND, P, RR, PER, 256>(L, st);
+#define SC_VC3D_SET(T, PER)                 \
+  SC_VC3(T, K_SCALE, PER, PAT_DIAMOND, 2)   \
+  SC_VC3(T, K_SCALE, PER, PAT_BOX, 2)       \
+  SC_VC3(T, K_ACCUM, PER, PAT_CROSS, 1)     \
+  SC_VC3(T, K_ACCUM, PER, PAT_BOX, 1)
+hipError_t part_varcoef3d(const SweepLaunch& L, hipStream_t st) {
+  if (L.ks->sym) return hipErrorInvalidValue;
+  const int key = SC_VKEY3(L.ks->pat, L.ks->R, L.kind);
+  if (L.dtype == SC_F64) {
+    if (L.periodic) { switch (key) { SC_VC3D_SET(double, true) default: break; } }
+    else { switch (key) { SC_VC3D_SET(double, false) default: break; } }
+  } else {
+    if (L.periodic) { switch (key) { SC_VC3D_SET(float, true) default: break; } }
+    else { switch (key) { SC_VC3D_SET(float, false) default: break; } }
   }
   return hipErrorInvalidValue;
 }

@@ -117,6 +117,8 @@ hipError_t part_solve3d_f32(const SweepLaunch& L, hipStream_t st);
 hipError_t part_apply3s(const SweepLaunch& L, hipStream_t st);
 hipError_t part_solve3s_f64(const SweepLaunch& L, hipStream_t st);
 hipError_t part_solve3s_f32(const SweepLaunch& L, hipStream_t st);
+hipError_t part_varcoef2d(const SweepLaunch& L, hipStream_t st);
+hipError_t part_varcoef3d(const SweepLaunch& L, hipStream_t st);
 
 // Vector layout of solver workspace: pointers address the interior
 // (0,0,0) element, rows of `pitch` elements, planes of `zpitch`.
@@ -176,6 +178,8 @@ void server_destroy(sc_server* s);
 // shared validation / set-up helpers (solver.cpp)
 sc_status check_grid(const sc_grid* g, const char* what);
 void* interior(const sc_grid* g);
+sc_status apply_varcoef(int nterms, const sc_stencil* const* inner, const sc_stencil* const* outer, double h,
+                        const sc_grid* M, const sc_grid* in, sc_grid* out, sc_bc bc, hipStream_t st);
 void fill_opts(const sc_solve_opts* in, sc_solve_opts* o);
 sc_status check_precision(int precision);
 sc_status check_ch(const sc_stencil* lap, const sc_ch_params* prm, int dim);

@@ -36,6 +36,8 @@ int sweep_blocks(const SweepLaunch& L) {
 namespace {
 
 hipError_t route(const SweepLaunch& L, hipStream_t st) {
+  if (L.kind == K_SCALE || L.kind == K_ACCUM)
+    return L.ks->dim == 2 ? part_varcoef2d(L, st) : part_varcoef3d(L, st);
   if (L.ks->dim == 2) {
     if (L.kind == K_APPLY) return L.dtype == SC_F64 ? part_apply2d_f64(L, st) : part_apply2d_f32(L, st);
     if (L.dtype == SC_F32) return part_solve2d_f32(L, st);

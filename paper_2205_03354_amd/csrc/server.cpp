@@ -340,7 +340,7 @@ sc_status make_spec(const sc_server* S, const sc_request* r, Request* q) {
     q->f.assign(r->f, r->f + np);
     if (r->u0) q->u0.assign(r->u0, r->u0 + np);
     if (r->g) {
-      q->g_halo = sc_stencil_radius(r->op);
+      q->g_halo = sp.ksA.R;
       int64_t ng = 1;
       for (int a = 0; a < r->dim; ++a) ng *= r->n[a] + 2 * q->g_halo;
       q->g.assign(r->g, r->g + ng);

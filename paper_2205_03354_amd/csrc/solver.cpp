@@ -636,7 +636,7 @@ sc_status apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_gr
     s->cached_ks = cached;
   }
   const KStencil& ks = *static_cast<const KStencil*>(cached.get());
-  const int rad = sc_stencil_radius(s);
+  const int rad = ks.R;  // the radius the kernel reads
   if (bc == SC_BC_HALO && in->halo < rad) {
     set_error("halo mode needs in->halo >= radius (%d < %d)", in->halo, rad);
     return SC_EINVAL;
@@ -649,6 +649,108 @@ sc_status apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_gr
   L.pout = out->pitch[0];
   L.zout = out->pitch[1];
   return launch(L, st);
+}
+
+// y = sum_t B_t(M * A_t(x)): per term, one sweep writes w = M * A_t(x) on
+// the grid plus the ring B_t reads (a library workspace), and one sweep
+// applies B_t to w, writing (first term) or accumulating into y.
+sc_status apply_varcoef(int nterms, const sc_stencil* const* inner, const sc_stencil* const* outer, double h,
+                        const sc_grid* M, const sc_grid* in, sc_grid* out, sc_bc bc, hipStream_t st) {
+  sc_status r;
+  if (nterms < 1 || nterms > 16 || !inner || !outer) {
+    set_error("nterms must be in 1..16 with inner and outer arrays");
+    return SC_EINVAL;
+  }
+  if ((r = check_grid(in, "in")) != SC_OK || (r = check_grid(out, "out")) != SC_OK ||
+      (r = check_grid(M, "mobility")) != SC_OK)
+    return r;
+  if (!same_shape(in, out) || !same_shape(in, M) || in->dtype != out->dtype || in->dtype != M->dtype) {
+    set_error("in, out and the coefficient grid must share dim, n and dtype");
+    return SC_EINVAL;
+  }
+  if (bc != SC_BC_PERIODIC && bc != SC_BC_HALO) {
+    set_error("unknown boundary mode %d", (int)bc);
+    return SC_EINVAL;
+  }
+  if (overlaps(in, out) || overlaps(M, out)) {
+    set_error("out overlaps an input in memory");
+    return SC_EINVAL;
+  }
+  int rA = 0, rB = 0;
+  std::vector<KStencil> ka(nterms), kb(nterms);
+  for (int t = 0; t < nterms; ++t) {
+    if (!inner[t] || !outer[t] || inner[t]->dim != in->dim || outer[t]->dim != in->dim) {
+      set_error("term %d: NULL stencil or dimension mismatch", t);
+      return SC_EINVAL;
+    }
+    if ((r = make_kstencil(inner[t], h, &ka[t])) != SC_OK || (r = make_kstencil(outer[t], h, &kb[t])) != SC_OK)
+      return r;
+    rA = std::max(rA, ka[t].R);
+    rB = std::max(rB, kb[t].R);
+  }
+  const bool per = bc == SC_BC_PERIODIC;
+  if (!per && (in->halo < rA + rB || M->halo < rB)) {
+    set_error("halo mode needs in->halo >= %d (inner + outer radius) and coefficient halo >= %d", rA + rB, rB);
+    return SC_EINVAL;
+  }
+  const int dim = in->dim;
+  const int wr = per ? 0 : rB;  // ring of the workspace
+  int64_t ne[3] = {in->n[0], in->n[1], in->n[2]};
+  for (int a = 0; a < dim; ++a) ne[a] += 2 * wr;
+  const Layout lay = make_layout(dim, in->n, wr, in->dtype);
+  const size_t bytes = vec_bytes(dim, in->n, wr, in->dtype);
+  void* wbuf = pool_alloc(bytes);
+  if (!wbuf) {
+    set_error("workspace allocation of %zu bytes failed", bytes);
+    return SC_ENOMEM;
+  }
+  const int64_t es = (int64_t)esize(in->dtype);
+  const int64_t pad = (256 - (wr * es) % 256) % 256;
+  const int64_t off_w = (dim == 3 ? wr * lay.zpitch : 0) + wr * lay.pitch + wr;
+  char* w_int = static_cast<char*>(wbuf) + pad + off_w * es;  // workspace interior
+  char* w_org = w_int - off_w * es;                            // its ring's first element
+  auto shifted = [&](const sc_grid* g) {                       // interior moved back by the ring
+    const int64_t o = (dim == 3 ? wr * g->pitch[1] : 0) + wr * g->pitch[0] + wr;
+    return static_cast<const char*>(interior(g)) - o * es;
+  };
+  sc_status res = SC_OK;
+  for (int t = 0; t < nterms && res == SC_OK; ++t) {
+    SweepLaunch L1 = sweep_on(K_SCALE, ka[t], per, in->dtype, ne);
+    L1.in = shifted(in);
+    L1.pin = in->pitch[0];
+    L1.zin = in->pitch[1];
+    L1.aux = shifted(M);
+    L1.paux = M->pitch[0];
+    L1.zaux = M->pitch[1];
+    L1.out = w_org;
+    L1.pout = lay.pitch;
+    L1.zout = lay.zpitch;
+    if ((res = launch(L1, st)) != SC_OK) break;
+    SweepLaunch L2 = sweep_on(t == 0 ? K_APPLY : K_ACCUM, kb[t], per, in->dtype, in->n);
+    L2.in = w_int;
+    L2.pin = lay.pitch;
+    L2.zin = lay.zpitch;
+    L2.out = interior(out);
+    L2.pout = out->pitch[0];
+    L2.zout = out->pitch[1];
+    L2.aux = interior(out);
+    L2.paux = out->pitch[0];
+    L2.zaux = out->pitch[1];
+    if (!per) {  // the workspace rows are padded (see make_layout); out is not
+      L2.x_range = true;
+      L2.in_xlo = -lay.halo_x;
+      L2.in_xhi = lay.xhi;
+      L2.aux_xhi = in->n[0];
+    }
+    res = launch(L2, st);
+  }
+  const hipError_t e = hipStreamSynchronize(st);  // the workspace goes back to the pool
+  pool_free(wbuf);
+  if (res == SC_OK && e != hipSuccess) {
+    set_error("device error: %s", hipGetErrorString(e));
+    res = SC_EDEVICE;
+  }
+  return res;
 }
 
 void fill_opts(const sc_solve_opts* in, sc_solve_opts* o) {
@@ -771,7 +873,7 @@ sc_status solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, con
   fill_opts(opts, &sp.o);
   if ((r = check_precision(sp.o.precision)) != SC_OK) return r;
   if ((r = make_kstencil(op, h, &sp.ksA)) != SC_OK) return r;
-  const int rad = sc_stencil_radius(op);
+  const int rad = sp.ksA.R;
   if (gr && gr->halo < rad) {
     set_error("g must carry a ring of width >= radius (%d < %d)", gr->halo, rad);
     return SC_EINVAL;

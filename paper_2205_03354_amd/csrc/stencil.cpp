@@ -226,8 +226,14 @@ sc_status make_kstencil(int dim, const std::vector<std::array<int32_t, 3>>& off,
   }
   const Cand* cands = dim == 2 ? kCand2 : kCand3;
   const int ncand = dim == 2 ? (int)(sizeof(kCand2) / sizeof(Cand)) : (int)(sizeof(kCand3) / sizeof(Cand));
+  // a kernel reads every tap of its pattern (zero weights included), so the
+  // pattern's radius must be the stencil's own: callers size rings by it
+  int radius = 1;  // a lone centre tap still runs a radius-1 kernel
+  for (const auto& o : off)
+    for (int a = 0; a < 3; ++a) radius = std::max(radius, std::abs((int)o[a]));
   int best = -1, best_taps = 1 << 30;
   for (int c = 0; c < ncand; ++c) {
+    if (cands[c].R != radius) continue;
     bool ok = true;
     for (const auto& o : off) {
       if (!in_pattern(cands[c].pat, cands[c].R, o[0], o[1], dim == 3 ? o[2] : 0) || (dim == 2 && o[2] != 0)) {

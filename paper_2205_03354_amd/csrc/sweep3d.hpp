@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(NT)
   constexpr int LPP = (PL + NT - 1) / NT;
   constexpr int B = 2 * R + 1;
   constexpr int NV = (RA + R + VEC) / VEC + ((RA + R + VEC) % VEC ? 1 : 0);
-  constexpr bool HAS_DOT = KIND != K_APPLY;
+  constexpr bool HAS_DOT = kind_has_dot(KIND);
   using V = typename VecT<T, VEC>::type;
   static_assert(NT % NTX == 0, "block must tile the x extent");
   static_assert((NV - 1) * VEC <= 2 * RA, "window reads must stay inside the LDS row");
@@ -159,6 +159,10 @@ __global__ void __launch_bounds__(NT)
             const T rr = a.aux[gz * a.zaux + gy * a.paux + col] - accv[v];
             a.out[gz * a.zout + gy * a.pout + col] = rr;
             dot += (double)rr * (double)rr;
+          } else if constexpr (KIND == K_SCALE) {
+            a.out[gz * a.zout + gy * a.pout + col] = a.aux[gz * a.zaux + gy * a.paux + col] * accv[v];
+          } else if constexpr (KIND == K_ACCUM) {
+            a.out[gz * a.zout + gy * a.pout + col] = a.aux[gz * a.zaux + gy * a.paux + col] + accv[v];
           } else if constexpr (KIND == K_CHRHS) {
             const T rr = a.in[gz * a.zin + gy * a.pin + col] + (T)a.c0 * accv[v];
             a.out[gz * a.zout + gy * a.pout + col] = rr;

@@ -45,9 +45,9 @@ __global__ void __launch_bounds__(64)
   constexpr int KF = (NCH + 63) / 64;     // chunk DMAs per plane
   constexpr int PLANE = NYR * W;          // elements per slot
   constexpr bool TWO = KIND == K_CGDIR;
-  constexpr bool AUX = KIND == K_RESID || KIND == K_BVPRHS;
+  constexpr bool AUX = kind_reads_aux(KIND);
   constexpr bool NEED_CEN = KIND == K_CGDIR || KIND == K_CHRHS;
-  constexpr bool HAS_DOT = KIND != K_APPLY;
+  constexpr bool HAS_DOT = kind_has_dot(KIND);
   constexpr int NRING = D + 2;
   constexpr int B = 2 * R + 1;
   constexpr int NV = (VPL + 2 * RA) / VPL;
@@ -229,7 +229,14 @@ __global__ void __launch_bounds__(64)
     } else if constexpr (AUX) {
       const V t = reinterpret_cast<const V*>(ringa + (slot * TY + j) * TXW)[lane];
 #pragma unroll
-      for (int v = 0; v < VPL; ++v) res[v] = t[v] - accv[v];
+      for (int v = 0; v < VPL; ++v) {
+        if constexpr (KIND == K_SCALE)
+          res[v] = t[v] * accv[v];
+        else if constexpr (KIND == K_ACCUM)
+          res[v] = t[v] + accv[v];
+        else
+          res[v] = t[v] - accv[v];
+      }
     } else if constexpr (KIND == K_CHRHS) {
 #pragma unroll
       for (int v = 0; v < VPL; ++v) res[v] = cenv[v] + (T)a.c0 * accv[v];

@@ -44,3 +44,13 @@ def biharmonic(dim: int, fourth_order: bool = False) -> Stencil:
     25-point (3D), or 33-point for the fourth-order factor in 2D."""
     L = laplacian(dim, fourth_order)
     return compose_stencil(L, L)
+
+
+def flux_terms(dim: int, inner: Stencil):
+    """Terms (D1_a o inner, D1_a) of div(M grad(inner f)) for apply_varcoef,
+    with the central first derivative D1 (Sec. 2.2.3)."""
+    terms = []
+    for a in range(dim):
+        d1 = first_derivative(dim, a)
+        terms.append((compose_stencil(d1, inner), d1))
+    return terms

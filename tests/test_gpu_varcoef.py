@@ -1,0 +1,125 @@
+"""GPU parity of the variable-coefficient composition sum_t B_t(M * A_t(x)).
+
+Bars: with M = 1 and integer inputs the result equals the constant composed
+stencil applied by the oracle, bit for bit (all weights are dyadic and the
+sums exact). With random inputs the error is measured against the magnitude
+of the summed terms (the same |B| (|M| (|A| |x|)) bound the two-stage sum
+can round against) and must be <= 1e-12 in FP64 and <= 1e-5 in FP32.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic as S
+from oracle import capi
+from oracle import problems as OP
+from oracle import rational as R
+from tests.gpu_util import abs_stencil, lib_stencil
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2205_03354_amd import _native
+
+    return _native
+
+
+def _lib_terms(native, terms):
+    return [(lib_stencil(native, A), lib_stencil(native, B)) for A, B in terms]
+
+
+def _scale(terms, M, x, mode, halo):
+    aterms = [(abs_stencil(A), abs_stencil(B)) for A, B in terms]
+    return float(np.max(OP.varcoef_apply(aterms, np.abs(M), np.abs(x), mode, halo)))
+
+
+def _gpu(native, terms, M, x, bc, halo, dtype, mob_halo=0):
+    xt = torch.from_numpy(x).to(DEV, dtype)
+    Mt = torch.from_numpy(M).to(DEV, dtype)
+    shape = tuple(s - 2 * halo for s in x.shape) if bc == native.SC_BC_HALO else x.shape
+    y = torch.full(shape, float("nan"), dtype=dtype, device=DEV)
+    native.apply_varcoef(_lib_terms(native, terms), Mt, xt, y, bc, halo=halo, mob_halo=mob_halo)
+    return y.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (77, 301)), (2, (35, 1000)), (3, (20, 17, 33)), (3, (40, 9, 70))])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_unit_mobility_integer_bit_exact(native, dim, shape, dtype):
+    L = R.laplacian(dim)
+    terms = OP.flux_terms(dim, L)
+    C = None
+    for A, B in terms:
+        t = R.compose(B, A)
+        C = t if C is None else R.add(C, t)
+    x = S.integer_field(shape, seed=21, lo=-64, hi=64)
+    got = _gpu(native, terms, np.ones(shape), x, native.SC_BC_PERIODIC, 0, dtype)
+    assert np.array_equal(got, capi.apply(C, x, capi.PERIODIC))
+    xh = S.integer_field(tuple(s + 6 for s in shape), seed=22, lo=-64, hi=64)
+    got = _gpu(native, terms, np.ones(tuple(s + 2 for s in shape)), xh, native.SC_BC_HALO, 3, dtype, mob_halo=1)
+    assert np.array_equal(got, capi.apply(C, xh, capi.HALO, 3))
+
+
+@pytest.mark.parametrize("dim,shape,fourth", [(2, (77, 301), False), (2, (130, 257), True), (2, (5, 6), False),
+                                              (3, (20, 17, 33), False), (3, (6, 5, 7), False)])
+def test_random_mobility_parity(native, dim, shape, fourth):
+    terms = OP.flux_terms(dim, R.laplacian(dim, fourth))
+    rA = max(A.radius() for A, _ in terms)
+    rB = max(B.radius() for _, B in terms)
+    x = S.uniform_field(shape, seed=31)
+    M = 1.0 + 0.5 * S.uniform_field(shape, seed=32)
+    ref = OP.varcoef_apply(terms, M, x, capi.PERIODIC)
+    got = _gpu(native, terms, M, x, native.SC_BC_PERIODIC, 0, torch.float64)
+    sc = _scale(terms, M, x, capi.PERIODIC, 0)
+    assert np.max(np.abs(got - ref)) / sc <= 1e-12
+    got32 = _gpu(native, terms, M, x, native.SC_BC_PERIODIC, 0, torch.float32)
+    assert np.max(np.abs(got32 - ref)) / sc <= 1e-5
+    halo = rA + rB
+    xh = S.uniform_field(tuple(s + 2 * halo for s in shape), seed=33)
+    Mh = 1.0 + 0.5 * S.uniform_field(tuple(s + 2 * rB for s in shape), seed=34)
+    ref = OP.varcoef_apply(terms, Mh, xh, capi.HALO, halo)
+    got = _gpu(native, terms, Mh, xh, native.SC_BC_HALO, halo, torch.float64, mob_halo=rB)
+    assert np.max(np.abs(got - ref)) / _scale(terms, Mh, xh, capi.HALO, halo) <= 1e-12
+
+
+def test_manufactured_order_on_gpu(native):
+    import math
+
+    terms = OP.flux_terms(2, R.laplacian(2))
+    lt = None
+    errs, hs = [], []
+    for N in (64, 128, 256):
+        h = 1.0 / N
+        c = np.arange(N) * h
+        X, Y = np.meshgrid(c, c, indexing="xy")
+        k = 2 * math.pi
+        f = np.sin(k * X) * np.sin(k * Y)
+        M = 1.0 + 0.5 * np.cos(k * X)
+        exact = -2 * k * k * (-0.5 * k * np.sin(k * X) * k * np.cos(k * X) * np.sin(k * Y)
+                              + M * (-2 * k * k) * f)
+        lt = _lib_terms(native, terms)
+        xt, Mt = torch.from_numpy(f).to(DEV), torch.from_numpy(M).to(DEV)
+        y = torch.empty_like(xt)
+        native.apply_varcoef(lt, Mt, xt, y, native.SC_BC_PERIODIC, h=h)
+        errs.append(float(np.max(np.abs(y.cpu().numpy() - exact)) / np.max(np.abs(exact))))
+        hs.append(h)
+    rate = math.log(errs[1] / errs[2]) / math.log(hs[1] / hs[2])
+    assert abs(rate - 2.0) < 0.1, (errs, rate)
+
+
+def test_varcoef_errors(native):
+    terms = OP.flux_terms(2, R.laplacian(2))
+    lt = _lib_terms(native, terms)
+    x = torch.zeros((12, 12), dtype=torch.float64, device=DEV)
+    M = torch.ones((10, 10), dtype=torch.float64, device=DEV)
+    y = torch.zeros((10, 10), dtype=torch.float64, device=DEV)
+    with pytest.raises(native.ScError):  # ring 1 < 3
+        native.apply_varcoef(lt, M, x, y, native.SC_BC_HALO, halo=1)
+    with pytest.raises(native.ScError):  # no terms
+        native.apply_varcoef([], M, y, y, native.SC_BC_PERIODIC)
+    with pytest.raises(native.ScError):  # out aliases in
+        native.apply_varcoef(lt, M, y, y, native.SC_BC_PERIODIC)
