@@ -80,6 +80,21 @@ typedef enum sc_bc { SC_BC_PERIODIC = 0, SC_BC_HALO = 1 } sc_bc;
  * Both mixed modes stop on the FP64 true residual. */
 typedef enum sc_precision { SC_PREC_F64 = 0, SC_PREC_F32_IR = 1, SC_PREC_F32_RU = 2 } sc_precision;
 
+/* Preconditioner of the biharmonic BVP's CG.
+ *   SC_PC_NONE          plain CG.
+ *   SC_PC_FASTPOISSON   M = L_D^2, L_D the 5/7-point Laplacian on the unknowns
+ *                       with a zero ring (the composition of Sec. 3.3 on the
+ *                       interior). The BVP operator differs from L_D^2 by a
+ *                       non-negative diagonal next to the boundary, so CG on
+ *                       M^-1 A needs few iterations at any grid size (10..25
+ *                       for 33..257 nodes per side). M^-1 is applied with the
+ *                       orthonormal sine transform along every axis (dense
+ *                       products on the device) and a pointwise division by
+ *                       the squared eigenvalues. In the mixed precisions the
+ *                       FP32 recurrence is preconditioned in FP32. Blocks of
+ *                       preconditioned iterations are not graph-captured. */
+typedef enum sc_precond { SC_PC_NONE = 0, SC_PC_FASTPOISSON = 1 } sc_precond;
+
 typedef struct sc_stencil sc_stencil;
 
 /*
@@ -208,7 +223,8 @@ typedef struct sc_solve_opts {
                            <= 0 selects 1e-4 (F32_IR) or 0.1 (F32_RU) */
   int32_t check_every;  /* CG iterations launched between host convergence checks */
   int32_t use_graph;    /* 1: replay each block of check_every iterations from a
-                           captured hipGraph (check_every even); 0: plain launches */
+                           captured hipGraph; 0: plain launches */
+  int32_t precond;      /* sc_precond (biharmonic BVP only; ignored for CH) */
 } sc_solve_opts;
 
 typedef struct sc_solve_stats {
@@ -220,7 +236,8 @@ typedef struct sc_solve_stats {
 } sc_solve_stats;
 
 /* Fill opts with defaults: tol 1e-10, max_iter 10^7, SC_PREC_F64,
- * inner_tol 0 (the precision's default), check_every 64, use_graph 1. */
+ * inner_tol 0 (the precision's default), check_every 64, use_graph 1,
+ * precond SC_PC_NONE. */
 void sc_solve_opts_default(sc_solve_opts* opts);
 
 /*

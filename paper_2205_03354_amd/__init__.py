@@ -10,6 +10,8 @@ from ._native import (  # noqa: F401
     ApplyPlan,
     SC_BC_HALO,
     SC_BC_PERIODIC,
+    SC_PC_FASTPOISSON,
+    SC_PC_NONE,
     SC_PREC_F32_IR,
     SC_PREC_F32_RU,
     SC_PREC_F64,

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libscomp.so")
 (SC_OK, SC_EINVAL, SC_EOVERFLOW, SC_EDEVICE, SC_ENOMEM, SC_ENOTCONV, SC_EBREAKDOWN, SC_EUNSUPPORTED,
  SC_ECANCELLED) = range(9)
 SC_REQ_BVP, SC_REQ_CH_STEP = 0, 1
+SC_PC_NONE, SC_PC_FASTPOISSON = 0, 1
 SC_F64, SC_F32 = 0, 1
 SC_BC_PERIODIC, SC_BC_HALO = 0, 1
 SC_PREC_F64, SC_PREC_F32_IR, SC_PREC_F32_RU = 0, 1, 2
@@ -45,7 +46,8 @@ class SCGrid(ctypes.Structure):
 
 class SCSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("precision", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("precond", ctypes.c_int32)]
 
 
 class SCSolveStats(ctypes.Structure):
@@ -293,7 +295,7 @@ class SolveStats:
     status: int
 
 
-def _opts(tol, max_iter, precision, inner_tol, check_every, use_graph=True) -> SCSolveOpts:
+def _opts(tol, max_iter, precision, inner_tol, check_every, use_graph=True, precond=SC_PC_NONE) -> SCSolveOpts:
     o = SCSolveOpts()
     lib.sc_solve_opts_default(ctypes.byref(o))
     o.tol = tol
@@ -302,6 +304,7 @@ def _opts(tol, max_iter, precision, inner_tol, check_every, use_graph=True) -> S
     o.inner_tol = inner_tol
     o.check_every = int(check_every)
     o.use_graph = 1 if use_graph else 0
+    o.precond = int(precond)
     return o
 
 
@@ -311,12 +314,12 @@ def _stats(s: SCSolveStats, status: int) -> SolveStats:
 
 def solve_biharmonic(op: Stencil, h: float, f, u, g=None, g_halo: int = 0, tol: float = 1e-10,
                      max_iter: int = 10**7, precision: int = SC_PREC_F64, inner_tol: float = 0.0,
-                     check_every: int = 64, use_graph: bool = True, raise_on_error: bool = True,
-                     stream=None) -> SolveStats:
+                     check_every: int = 64, use_graph: bool = True, precond: int = SC_PC_NONE,
+                     raise_on_error: bool = True, stream=None) -> SolveStats:
     """A u = f at the unknowns with the ring prescribed by g (see scomp.h)."""
     gf, gu = grid_of(f, 0), grid_of(u, 0)
     gg = ctypes.byref(grid_of(g, g_halo)) if g is not None else None
-    o = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph)
+    o = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph, precond)
     st = SCSolveStats()
     status = lib.sc_solve_biharmonic(op.handle, float(h), ctypes.byref(gf), gg, ctypes.byref(o), ctypes.byref(gu),
                                      ctypes.byref(st), _stream(stream))
@@ -359,11 +362,12 @@ class Server:
 
     def __init__(self, hbm_budget: int = 0, max_slots: int = 16, tol: float = 1e-10,
                  precision: int = SC_PREC_F64, inner_tol: float = 0.0, check_every: int = 64,
-                 use_graph: bool = True, max_iter: int = 10**7, fake_device: bool = False):
+                 use_graph: bool = True, max_iter: int = 10**7, fake_device: bool = False,
+                 precond: int = SC_PC_NONE):
         o = SCServerOpts()
         o.hbm_budget = int(hbm_budget)
         o.max_slots = int(max_slots)
-        o.solve = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph)
+        o.solve = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph, precond)
         o.fake_device = 1 if fake_device else 0
         h = ctypes.c_void_p()
         _check(lib.sc_server_create(ctypes.byref(o), ctypes.byref(h)))

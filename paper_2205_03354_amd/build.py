@@ -42,7 +42,7 @@ def _jobs():
 
 def _units():
     units = []
-    for name in ("abi.cpp", "stencil.cpp", "solver.cpp", "server.cpp"):
+    for name in ("abi.cpp", "stencil.cpp", "solver.cpp", "server.cpp", "precond.cpp"):
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name + ".o"), ["-x", "hip"]))
     for name in ("launch_host.hip", "elementwise.hip"):
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name + ".o"), []))
@@ -74,7 +74,8 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError("hipcc failed:\n" + "\n".join(r[1] for r in failed))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + [u[1] for u in units]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + [u[1] for u in units] + \
+        ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stderr)

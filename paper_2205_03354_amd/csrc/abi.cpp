@@ -111,6 +111,7 @@ void sc_solve_opts_default(sc_solve_opts* o) {
   o->inner_tol = 0.0;
   o->check_every = 64;
   o->use_graph = 1;
+  o->precond = SC_PC_NONE;
 }
 
 sc_status sc_solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, const sc_grid* g,

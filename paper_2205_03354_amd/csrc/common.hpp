@@ -111,7 +111,8 @@ struct alignas(64) DevScalars {
   long long iter;   // iterations performed
   int done;         // 0 running, 1 recurrence converged, 2 breakdown
   unsigned int ticket;
-  double pad[5];
+  double rz;        // preconditioned CG: <r, M^-1 r>
+  double pad[4];
 };
 
 // ---------------------------------------------------------------------------

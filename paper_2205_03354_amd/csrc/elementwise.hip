@@ -177,7 +177,101 @@ int elem_blocks(const int64_t* n) {
   return (int)(rows < kElemBlocks ? rows : kElemBlocks);
 }
 
+// t /= (lx_i + ly_j + lz_k)^2 : the squared Dirichlet Laplacian in its
+// sine eigenbasis (lz = 0 in 2D)
+template <typename T>
+__global__ void __launch_bounds__(kNT)
+    pc_scale_kernel(T* __restrict__ t, int64_t pitch, int64_t zpitch, int64_t n0, int64_t n1, int64_t n2,
+                    const double* __restrict__ lx, const double* __restrict__ ly, const double* __restrict__ lz,
+                    const DevScalars* s) {
+  if (s->done) return;
+  const RowRange rr = block_rows(n1 * n2);
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t k = rho / n1, j = rho - k * n1;
+    const double lyz = ly[j] + (lz ? lz[k] : 0.0);
+    T* row = t + k * zpitch + j * pitch;
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) {
+      const double l = lx[i] + lyz;
+      row[i] = (T)((double)row[i] / (l * l));
+    }
+  }
+}
+
+// rz = <r, z>; beta = rz / rz_old (0 when starting), rz_old = rz
+template <typename T>
+__global__ void __launch_bounds__(kNT)
+    pc_dot_kernel(const T* __restrict__ r, const T* __restrict__ z, int64_t pitch, int64_t zpitch, int64_t n0,
+                  int64_t n1, int64_t n2, DevScalars* s, int start, double* partials) {
+  if (s->done) return;
+  const RowRange rr = block_rows(n1 * n2);
+  double dot = 0.0;
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t o = row_offset(rho, n1, pitch, zpitch);
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) dot += (double)r[o + i] * (double)z[o + i];
+  }
+  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s->ticket, [&](double total) {
+    s->beta = (start || !(s->rz > 0.0)) ? 0.0 : total / s->rz;
+    s->rz = total;
+    if (!(total > 0.0)) s->done = 2;  // the preconditioner lost positivity
+  });
+}
+
+// S[j][k] = sqrt(2/(m+1)) sin(pi (j+1)(k+1)/(m+1)), the angle reduced
+// exactly in integers; lam[k] = -(4/h^2) sin^2(pi (k+1) / (2(m+1)))
+template <typename T>
+__global__ void __launch_bounds__(kNT) pc_init_kernel(T* __restrict__ S, double* __restrict__ lam, int64_t m, double h) {
+  const int64_t tid = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kNT;
+  const double c0 = sqrt(2.0 / (double)(m + 1));
+  const int64_t period = 2 * (m + 1);
+  if (S)
+    for (int64_t e = tid; e < m * m; e += stride) {
+      const int64_t j = e / m, k = e - j * m;
+      const int64_t t = ((j + 1) * (k + 1)) % period;
+      S[e] = (T)(c0 * sin(M_PI * (double)t / (double)(m + 1)));
+    }
+  for (int64_t k = tid; k < m; k += stride) {
+    const double sk = sin(M_PI * (double)(k + 1) / (double)period);
+    lam[k] = -4.0 / (h * h) * sk * sk;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_pc_init(int dtype, void* S, double* lam, int64_t m, double h, hipStream_t st) {
+  int64_t nb = (m * m + kNT - 1) / kNT;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  if (dtype == SC_F64)
+    hipLaunchKernelGGL(pc_init_kernel<double>, dim3((unsigned)nb), dim3(kNT), 0, st, (double*)S, lam, m, h);
+  else
+    hipLaunchKernelGGL(pc_init_kernel<float>, dim3((unsigned)nb), dim3(kNT), 0, st, (float*)S, lam, m, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_pc_scale(int dtype, void* t, const Layout& lay, const int64_t* n, const double* lx,
+                           const double* ly, const double* lz, const DevScalars* s, hipStream_t st) {
+  const int nb = elem_blocks(n);
+  if (dtype == SC_F64)
+    hipLaunchKernelGGL(pc_scale_kernel<double>, dim3(nb), dim3(kNT), 0, st, (double*)t, lay.pitch, lay.zpitch, n[0],
+                       n[1], n[2], lx, ly, lz, s);
+  else
+    hipLaunchKernelGGL(pc_scale_kernel<float>, dim3(nb), dim3(kNT), 0, st, (float*)t, lay.pitch, lay.zpitch, n[0],
+                       n[1], n[2], lx, ly, lz, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_pc_dot(int dtype, const void* r, const void* z, const Layout& lay, const int64_t* n,
+                         DevScalars* s, int start, double* partials, hipStream_t st) {
+  const int nb = elem_blocks(n);
+  if (dtype == SC_F64)
+    hipLaunchKernelGGL(pc_dot_kernel<double>, dim3(nb), dim3(kNT), 0, st, (const double*)r, (const double*)z,
+                       lay.pitch, lay.zpitch, n[0], n[1], n[2], s, start, partials);
+  else
+    hipLaunchKernelGGL(pc_dot_kernel<float>, dim3(nb), dim3(kNT), 0, st, (const float*)r, (const float*)z,
+                       lay.pitch, lay.zpitch, n[0], n[1], n[2], s, start, partials);
+  return hipGetLastError();
+}
 
 hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
                             const Layout& lay, const int64_t* n, DevScalars* s, double* partials,

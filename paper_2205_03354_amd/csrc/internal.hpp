@@ -143,6 +143,13 @@ hipError_t launch_ir_prepare(const double* r64, const Layout& l64, float* r32, f
                              const Layout& l32, const int64_t* n, DevScalars* s64,
                              DevScalars* s32, double inner_tol2, int keep_direction,
                              double* partials, hipStream_t st);
+// Preconditioner pieces: t /= (lx_i + ly_j + lz_k)^2 (lz may be null), and
+// rz = <r, z>, beta = rz / rz_old (0 when start), both skipped once done.
+hipError_t launch_pc_init(int dtype, void* S, double* lam, int64_t m, double h, hipStream_t st);
+hipError_t launch_pc_scale(int dtype, void* t, const Layout& lay, const int64_t* n, const double* lx,
+                           const double* ly, const double* lz, const DevScalars* s, hipStream_t st);
+hipError_t launch_pc_dot(int dtype, const void* r, const void* z, const Layout& lay, const int64_t* n,
+                         DevScalars* s, int start, double* partials, hipStream_t st);
 // x64 += s32->scale * d32
 hipError_t launch_ir_update(double* x64, const Layout& l64, const float* d32, const Layout& l32,
                             const int64_t* n, const DevScalars* s32, hipStream_t st);
@@ -182,6 +189,7 @@ sc_status apply_varcoef(int nterms, const sc_stencil* const* inner, const sc_ste
                         const sc_grid* M, const sc_grid* in, sc_grid* out, sc_bc bc, hipStream_t st);
 void fill_opts(const sc_solve_opts* in, sc_solve_opts* o);
 sc_status check_precision(int precision);
+sc_status check_opts(const sc_solve_opts& o);
 sc_status check_ch(const sc_stencil* lap, const sc_ch_params* prm, int dim);
 sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* ksA, KStencil* ksL);
 

@@ -327,6 +327,7 @@ sc_status make_spec(const sc_server* S, const sc_request* r, Request* q) {
     fill_opts(&o, &sp.o);
   }
   sp.dim = r->dim;
+  sp.h = r->kind == SC_REQ_CH_STEP ? r->ch.h : r->h;
   for (int a = 0; a < 3; ++a) sp.n[a] = r->n[a];
   const int64_t np = r->n[0] * r->n[1] * r->n[2];
   sc_status s;
@@ -383,7 +384,7 @@ sc_status server_create(const sc_server_opts* opts, sc_server** out) {
   S->opts = *opts;
   fill_opts(&opts->solve, &S->opts.solve);
   S->inner_tol_set = opts->solve.inner_tol > 0;
-  if (check_precision(S->opts.solve.precision) != SC_OK) return SC_EINVAL;
+  if (check_opts(S->opts.solve) != SC_OK) return SC_EINVAL;
   S->slots.resize(opts->max_slots);
   if (!opts->fake_device) {
     SC_HIP_CHECK(hipGetDevice(&S->device));

@@ -172,6 +172,10 @@ size_t task_footprint(const TaskSpec& sp) {
     b = 6 * v64 + 5 * v32;  // x b r64 (+ p0 p1 q if it falls back to FP64) | r d p0 p1 q
   else
     b = 6 * v64;            // x b r p0 p1 q
+  if (sp.kind == TASK_BVP && sp.o.precond == SC_PC_FASTPOISSON) {  // z and scratch, tables
+    b += 2 * v64 + fastpoisson_bytes(sp.dim, sp.n, SC_F64);
+    if (f32) b += 2 * v32 + fastpoisson_bytes(sp.dim, sp.n, SC_F32);
+  }
   b += 4096 + (size_t)partial_slots(sp) * 3 * sizeof(double);
   return b;
 }
@@ -212,6 +216,7 @@ sc_status SolveTask::init(const TaskSpec& spec, hipStream_t st) {
   f32_ = spec.o.precision != SC_PREC_F64;
   ru_ = spec.o.precision == SC_PREC_F32_RU;
   restart_ = true;
+  pc_ = spec.kind == TASK_BVP && spec.o.precond == SC_PC_FASTPOISSON;
   halo_ = periodic_ ? 0 : spec.ksA.R;
   h64_ = pinned_pair_alloc();
   if (!h64_) {
@@ -240,7 +245,31 @@ sc_status SolveTask::init(const TaskSpec& spec, hipStream_t st) {
     if ((s = make(&r32_, SC_F32)) != SC_OK || (s = make(&d32_, SC_F32)) != SC_OK) return s;
   }
   if ((s = make(&p_[0], vt)) != SC_OK || (s = make(&p_[1], vt)) != SC_OK || (s = make(&q_, vt)) != SC_OK) return s;
+  if (pc_ && (s = make_pc(f32_)) != SC_OK) return s;
   phase_ = P_NONE;
+  return SC_OK;
+}
+
+sc_status SolveTask::make_pc(bool f32) {
+  sc_status s;
+  if (f32) {
+    if ((s = make(&z32_, SC_F32)) != SC_OK || (s = make(&t32_, SC_F32)) != SC_OK) return s;
+    return pc32_.init(spec_.dim, spec_.n, spec_.h, SC_F32, st_);
+  }
+  if ((s = make(&z64_, SC_F64)) != SC_OK || (s = make(&t64_, SC_F64)) != SC_OK) return s;
+  return pc64_.init(spec_.dim, spec_.n, spec_.h, SC_F64, st_);
+}
+
+// z = M^-1 r and <r, z> (beta = <r, z> / <r_old, z_old>, or 0 when starting)
+sc_status SolveTask::precondition(bool f32, int start) {
+  sc_status s;
+  if (f32) {
+    if ((s = pc32_.apply(r32_.base, z32_.base, t32_.base, r32_.lay, d32s_, st_)) != SC_OK) return s;
+    SC_HIP_CHECK(launch_pc_dot(SC_F32, r32_.base, z32_.base, r32_.lay, spec_.n, d32s_, start, partials_, st_));
+    return SC_OK;
+  }
+  if ((s = pc64_.apply(r64_.base, z64_.base, t64_.base, r64_.lay, d64_, st_)) != SC_OK) return s;
+  SC_HIP_CHECK(launch_pc_dot(SC_F64, r64_.base, z64_.base, r64_.lay, spec_.n, d64_, start, partials_, st_));
   return SC_OK;
 }
 
@@ -328,6 +357,23 @@ sc_status SolveTask::enqueue_block(bool f32) {
     cur_ = 1 - cur_;
     return SC_OK;
   };
+  if (pc_) {
+    // p = z + beta p; q = A p; alpha = <r, z> / <p, q>; x, r update; z = M^-1 r.
+    // The transforms are library GEMMs that ignore the device stop flag,
+    // so blocks are short and are not captured.
+    Vec& z = f32 ? z32_ : z64_;
+    const int64_t k_run = std::min<int64_t>(std::min(K, 4), left);
+    for (int64_t k = 0; k < k_run; ++k) {
+      sc_status s = sweep(K_CGDIR, dtype, spec_.ksA, z.base, &z.lay, p_[cur_].base, nullptr, p_[1 - cur_].base,
+                          q_.base, r.lay, 1, 0, 0, 0, ds);
+      if (s != SC_OK) return s;
+      SC_HIP_CHECK(launch_cg_update(dtype, x.base, r.base, p_[1 - cur_].base, q_.base, x.lay, spec_.n, ds,
+                                    partials_, st_));
+      cur_ = 1 - cur_;
+      if ((s = precondition(f32, 0)) != SC_OK) return s;
+    }
+    return enqueue_read(f32);
+  }
   if (spec_.o.use_graph && left >= K) {
     hipGraphExec_t& ge = graph_[gi][cur_];
     const int cur0 = cur_;
@@ -388,6 +434,7 @@ sc_status SolveTask::start(const GridView& u0, const GridView& f, const GridView
   best_ = HUGE_VAL;
   if (!f32_) {
     if ((s = enqueue_residual(1)) != SC_OK) return s;
+    if (pc_ && (s = precondition(false, 1)) != SC_OK) return s;
     phase_ = P_CHECK64;
     return enqueue_read(false);
   }
@@ -421,7 +468,10 @@ sc_status SolveTask::fall_back_to_f64() {
   fell_back_ = true;
   stalled_ = 0;
   best_ = HUGE_VAL;
-  if ((s = enqueue_residual(1)) != SC_OK || (s = enqueue_read(false)) != SC_OK) return s;
+  if (pc_ && (s = make_pc(false)) != SC_OK) return s;
+  if ((s = enqueue_residual(1)) != SC_OK) return s;
+  if (pc_ && (s = precondition(false, 1)) != SC_OK) return s;
+  if ((s = enqueue_read(false)) != SC_OK) return s;
   phase_ = P_CHECK64;
   return SC_OK;
 }
@@ -460,7 +510,9 @@ sc_status SolveTask::advance(bool* done) {
         if ((s = enqueue_residual(0)) != SC_OK || (s = enqueue_read(false)) != SC_OK) return s;
         phase_ = P_FINAL;
       } else if (h64_->done == 1) {
-        if ((s = enqueue_residual(1)) != SC_OK || (s = enqueue_read(false)) != SC_OK) return s;
+        if ((s = enqueue_residual(1)) != SC_OK) return s;
+        if (pc_ && (s = precondition(false, 1)) != SC_OK) return s;
+        if ((s = enqueue_read(false)) != SC_OK) return s;
         ++outer_;
         phase_ = P_CHECK64;
       } else if (h64_->iter >= o.max_iter) {
@@ -488,6 +540,7 @@ sc_status SolveTask::advance(bool* done) {
         SC_HIP_CHECK(launch_ir_prepare((const double*)r64_.base, r64_.lay, (float*)r32_.base, (float*)d32_.base,
                                        r32_.lay, spec_.n, d64_, d32s_, o.inner_tol * o.inner_tol, keep, partials_,
                                        st_));
+        if (pc_ && (s = precondition(true, keep ? 0 : 1)) != SC_OK) return s;
         restart_ = false;
         inner_keep_ = keep;
         inner_start_ = h32_->iter;
@@ -770,6 +823,14 @@ sc_status check_precision(int precision) {
   return SC_OK;
 }
 
+sc_status check_opts(const sc_solve_opts& o) {
+  if (o.precond != SC_PC_NONE && o.precond != SC_PC_FASTPOISSON) {
+    set_error("unknown preconditioner %d", o.precond);
+    return SC_EINVAL;
+  }
+  return check_precision(o.precision);
+}
+
 // The operator of one Cahn-Hilliard step, I + dt eps^2 L o L - dt S L,
 // composed exactly and combined once in extended precision.
 sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* ksA, KStencil* ksL) {
@@ -871,7 +932,7 @@ sc_status solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, con
   }
   TaskSpec sp;
   fill_opts(opts, &sp.o);
-  if ((r = check_precision(sp.o.precision)) != SC_OK) return r;
+  if ((r = check_opts(sp.o)) != SC_OK) return r;
   if ((r = make_kstencil(op, h, &sp.ksA)) != SC_OK) return r;
   const int rad = sp.ksA.R;
   if (gr && gr->halo < rad) {
@@ -880,6 +941,7 @@ sc_status solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, con
   }
   if ((r = blocking_stream(st, &st)) != SC_OK) return r;
   sp.kind = TASK_BVP;
+  sp.h = h;
   sp.dim = u->dim;
   for (int a = 0; a < 3; ++a) sp.n[a] = u->n[a];
   SolveTask t;
@@ -910,13 +972,14 @@ sc_status ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_solve
   if ((r = check_ch(lap, prm, u->dim)) != SC_OK) return r;
   TaskSpec sp;
   fill_opts(opts, &sp.o);
-  if ((r = check_precision(sp.o.precision)) != SC_OK) return r;
+  if ((r = check_opts(sp.o)) != SC_OK) return r;
   if ((r = ch_operator(lap, prm, &sp.ksA, &sp.ksL)) != SC_OK) return r;
   sp.kind = TASK_CH;
   sp.dim = u->dim;
   for (int a = 0; a < 3; ++a) sp.n[a] = u->n[a];
   sp.dt = prm->dt;
   sp.S = prm->S;
+  sp.h = prm->h;
   if ((r = blocking_stream(st, &st)) != SC_OK) return r;
   SolveTask t;
   if ((r = t.init(sp, st)) != SC_OK) return r;

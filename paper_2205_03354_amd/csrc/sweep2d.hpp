@@ -88,7 +88,7 @@ __device__ __forceinline__ void finalize(DevScalars* s, double total, double tol
     if (!(total > 0.0) || !__builtin_isfinite(total)) {
       s->done = 2;
     } else {
-      s->alpha = s->rr / total;
+      s->alpha = (flag ? s->rz : s->rr) / total;  // flag: preconditioned, alpha = <r, z> / <p, A p>
     }
   } else if constexpr (KIND == K_RESID) {
     s->rr_true = total;

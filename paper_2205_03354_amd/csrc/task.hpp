@@ -31,11 +31,35 @@ struct TaskSpec {
   KStencil ksL;        // TASK_CH: the Laplacian (scaled by h^-2)
   double dt = 0.0;     // TASK_CH
   double S = 0.0;      // TASK_CH
+  double h = 0.0;      // grid spacing (the fast-Poisson preconditioner's eigenvalues)
   sc_solve_opts o{};
 };
 
 // Device bytes a task of this shape holds while it is alive.
 size_t task_footprint(const TaskSpec& spec);
+
+// Fast-Poisson preconditioner z = L_D^-2 r (see precond.cpp).
+class FastPoisson {
+ public:
+  FastPoisson() = default;
+  FastPoisson(const FastPoisson&) = delete;
+  FastPoisson& operator=(const FastPoisson&) = delete;
+  ~FastPoisson();
+  // Tables for the n unknowns per axis with spacing h (enqueued on st).
+  sc_status init(int dim, const int64_t* n, double h, int dtype, hipStream_t st);
+  // z = M^-1 r on the interiors of r, z, tmp (all of layout lay); the
+  // scaling kernel is skipped once s->done is set.
+  sc_status apply(const void* r, void* z, void* tmp, const Layout& lay, const DevScalars* s, hipStream_t st) const;
+
+ private:
+  int dim_ = 2;
+  int dtype_ = SC_F64;
+  int64_t n_[3] = {1, 1, 1};
+  void* S_[3] = {nullptr, nullptr, nullptr};
+  double* lam_[3] = {nullptr, nullptr, nullptr};
+  std::vector<void*> allocs_;
+};
+size_t fastpoisson_bytes(int dim, const int64_t* n, int dtype);
 
 class SolveTask {
  public:
@@ -72,6 +96,8 @@ class SolveTask {
   sc_status enqueue_residual(int flag);
   sc_status enqueue_read(bool both);
   sc_status fall_back_to_f64();
+  sc_status make_pc(bool f32);
+  sc_status precondition(bool f32, int start);
   void finish(sc_status s);
   sc_status sweep(int kind, int dtype, const KStencil& ks, const void* in, const Layout* lin, const void* in2,
                   const void* aux, void* out, void* out2, const Layout& lout, int flag, double c0, double c1,
@@ -108,6 +134,9 @@ class SolveTask {
   double stretch_best_ = 0.0;  // smallest FP32 recursive rr seen in the running stretch
   int stretch_idle_ = 0;       // blocks since it last halved
   bool fell_back_ = false;     // a mixed-precision solve that continued in FP64
+  bool pc_ = false;            // preconditioned CG (BVP, fast-Poisson)
+  FastPoisson pc64_, pc32_;
+  Vec z64_, t64_, z32_, t32_;  // z = M^-1 r and its scratch, per precision
   sc_solve_stats stats_{};
 };
 

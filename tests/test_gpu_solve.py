@@ -182,3 +182,67 @@ def test_ch_mass_energy_gpu(native, prec):
         assert E <= E_prev + 1e-14 * abs(E_prev)
         E_prev = E
     assert E_prev < E0
+
+
+# --------------------------------------------------------------- preconditioned
+@pytest.mark.parametrize("N", [17, 33, 65, 129])
+@pytest.mark.parametrize("prec", ["f64", "f32ir", "f32ru"])
+def test_bvp2d_fast_poisson_parity(native, N, prec):
+    # Same bars as the plain solve; the preconditioner must also cut the
+    # iteration count to a few dozen at every size (plain CG: 43..2268).
+    precision = _PREC[prec](native)
+    bvp, x, st = _gpu_bvp(native, 2, N, precision, precond=native.SC_PC_FASTPOISSON)
+    op = R.biharmonic(2)
+    b = OP.bvp_rhs(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert OP.true_relres(op, x, b, capi.ZERO_RING, bvp.h) <= 1e-10
+    xo, it, rel_o, rc = OP.bvp_solve(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert np.max(np.abs(x - xo)) / np.max(np.abs(xo)) <= 1e-6
+    if prec == "f64":
+        assert st.iterations <= 30, st.iterations
+    else:
+        assert st.iterations <= 150, st.iterations
+
+
+@pytest.mark.parametrize("n", [7, 15, 31])
+@pytest.mark.parametrize("prec", ["f64", "f32ru"])
+def test_bvp3d_fast_poisson_parity(native, n, prec):
+    precision = _PREC[prec](native)
+    bvp, x, st = _gpu_bvp(native, 3, n, precision, precond=native.SC_PC_FASTPOISSON)
+    op = R.biharmonic(3)
+    b = OP.bvp_rhs(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert OP.true_relres(op, x, b, capi.ZERO_RING, bvp.h) <= 1e-10
+    xo, it, rel_o, rc = OP.bvp_solve(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert np.max(np.abs(x - xo)) / np.max(np.abs(xo)) <= 1e-6
+    if prec == "f64":
+        assert st.iterations <= 40, st.iterations
+
+
+def test_fast_poisson_fourth_order_operator(native):
+    # The 33-point operator (the 4th-order Laplacian composed with itself)
+    # with the 5-point-based preconditioner: spectrally equivalent, so still
+    # few iterations, and the same solution as the oracle's CG.
+    from paper_2205_03354_amd import stencils
+
+    bvp = S.biharmonic_bvp(2, 65, halo=4)
+    f = torch.from_numpy(bvp.f).to(DEV)
+    g = torch.from_numpy(bvp.g).to(DEV)
+    u = torch.zeros_like(f)
+    st = native.solve_biharmonic(stencils.biharmonic(2, True), bvp.h, f, u, g=g, g_halo=4, tol=1e-10,
+                                 precond=native.SC_PC_FASTPOISSON)
+    op = R.biharmonic(2, True)
+    x = u.cpu().numpy()
+    b = OP.bvp_rhs(op, bvp.f, bvp.g, 4, bvp.h)
+    assert OP.true_relres(op, x, b, capi.ZERO_RING, bvp.h) <= 1e-10
+    xo, *_ = OP.bvp_solve(op, bvp.f, bvp.g, 4, bvp.h)
+    assert np.max(np.abs(x - xo)) / np.max(np.abs(xo)) <= 1e-6
+    assert st.iterations <= 80, st.iterations
+
+
+def test_fast_poisson_rejects_unknown_option(native):
+    from paper_2205_03354_amd import stencils
+
+    bvp = S.biharmonic_bvp(2, 17)
+    f = torch.from_numpy(bvp.f).to(DEV)
+    u = torch.zeros_like(f)
+    with pytest.raises(native.ScError):
+        native.solve_biharmonic(stencils.biharmonic(2), bvp.h, f, u, precond=7)
