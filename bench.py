@@ -10,12 +10,18 @@ Infinity Cache. Metric: algorithmic GB/s = 16 bytes per grid point (read x
 once, write y once) / time.
 
 Also reported (measured outside the timed steps, same process):
-* "roofline": the apply kernel's average duration from HIP events on the
-  stream it runs on, against the 8 TB/s HBM3E peak;
+* "roofline": the apply kernel's average duration from HIP events recorded
+  around each timed launch on the stream it runs on, against the 8 TB/s
+  HBM3E peak, and the HBM traffic from the committed counter profile;
 * "cpu_baseline": the oracle's naive apply (C, OpenMP) on the host cores;
-* "solves": biharmonic BVP solves/s with p50/p99 latency (2D 65^2 grid, FP64
-  CG and FP32 CG + FP64 refinement, to a 1e-10 true relative residual);
-* "ch": Cahn-Hilliard steps on a 1024^2 periodic grid.
+* "solves": 2D biharmonic BVP solves/s with p50/p99 latency (65^2 nodes,
+  plain and fast-Poisson preconditioned CG, FP64 and FP32 variants, to a
+  1e-10 true relative residual);
+* "ch": Cahn-Hilliard steps at 1024^2 and 256^3;
+* "bvp": preconditioned BVP solves at 257..2049^2 and 63..255^3;
+* "varcoef": the variable-coefficient operator div(M grad(Lap x)) at 4097^2;
+* "serve": the request server against one-at-a-time solves on a Poisson
+  stream of BVPs and CH steps.
 """
 
 from __future__ import annotations
@@ -33,10 +39,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# serving stream (sizes scaled down from 64..2048 / 32..192: without a
-# preconditioner the largest BVPs take tens of seconds each)
-SERVE_BVP_NODES = (33, 193)
-SERVE_CH_SIDE = (32, 96)
+# serving stream: BVP grids of 64..2048 nodes per side (solved with the
+# fast-Poisson preconditioner), CH steps on 32^3..192^3
+SERVE_BVP_NODES = (64, 2048)
+SERVE_CH_SIDE = (32, 192)
 SERVE_SLOTS = 16
 SERVE_LOAD = 0.7
 N_GRID = 4097
@@ -107,8 +113,9 @@ def solver_bench(native, torch, reps: int):
     f = torch.from_numpy(bvp.f).to(dev)
     g = torch.from_numpy(bvp.g).to(dev)
     op = stencils.biharmonic(2)
-    for name, prec in (("f64", native.SC_PREC_F64), ("f32_ir", native.SC_PREC_F32_IR),
-                       ("f32_ru", native.SC_PREC_F32_RU)):
+    for name, prec, pc in (("f64", native.SC_PREC_F64, 0), ("f32_ir", native.SC_PREC_F32_IR, 0),
+                           ("f32_ru", native.SC_PREC_F32_RU, 0), ("f64_pcg", native.SC_PREC_F64, 1),
+                           ("f32_ru_pcg", native.SC_PREC_F32_RU, 1)):
         lat = []
         its = 0
         rel = 0.0
@@ -116,7 +123,7 @@ def solver_bench(native, torch, reps: int):
             u = torch.zeros_like(f)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st = native.solve_biharmonic(op, bvp.h, f, u, g=g, g_halo=2, tol=1e-10, precision=prec)
+            st = native.solve_biharmonic(op, bvp.h, f, u, g=g, g_halo=2, tol=1e-10, precision=prec, precond=pc)
             t1 = time.perf_counter()
             if i > 0:
                 lat.append(t1 - t0)
@@ -126,7 +133,8 @@ def solver_bench(native, torch, reps: int):
                      "p50_ms": round(1e3 * statistics.median(lat), 3),
                      "p99_ms": round(1e3 * lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)], 3),
                      "iterations": its, "rel_residual": rel}
-    return {"workload": "2D biharmonic BVP, 65^2 nodes (63^2 unknowns), 13-point L o L, to 1e-10", **out}
+    return {"workload": "2D biharmonic BVP, 65^2 nodes (63^2 unknowns), 13-point L o L, to 1e-10; plain CG "
+                        "and fast-Poisson preconditioned CG (_pcg)", **out}
 
 
 def ch_bench(native, torch, steps: int):
@@ -156,30 +164,46 @@ def ch_bench(native, torch, steps: int):
     return res
 
 
-def bvp3d_bench(native, torch):
-    """3D biharmonic BVPs (25-point 7-point-Laplacian composition), solves
-    to a 1e-10 true relative residual, FP64 and FP32 with reliable updates."""
+def bvp_pcg_bench(native, torch):
+    """Biharmonic BVPs at the configurations' sizes with the fast-Poisson
+    preconditioner (2D 13-point and 3D 25-point L o L), to a 1e-10 true
+    relative residual; one solve per size and precision after a warm-up."""
     import synthetic as S
     from paper_2205_03354_amd import stencils
 
     dev = torch.device("cuda:0")
-    op = stencils.biharmonic(3)
-    res = {"workload": "3D biharmonic BVP, sin(pi x) sin(pi y) sin(pi z), n^3 unknowns, 2-ring from the exact u"}
-    for n in (63, 127):
-        bvp = S.biharmonic_bvp(3, n)
-        f = torch.from_numpy(bvp.f).to(dev)
-        g = torch.from_numpy(bvp.g).to(dev)
-        out = {}
-        for name, prec in (("f64", native.SC_PREC_F64), ("f32_ru", native.SC_PREC_F32_RU)):
-            u = torch.zeros_like(f)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = native.solve_biharmonic(op, bvp.h, f, u, g=g, g_halo=bvp.halo, tol=1e-10, precision=prec)
-            dt = time.perf_counter() - t0
-            err = float((u.cpu() - torch.from_numpy(bvp.u)).abs().max())
-            out[name] = {"ms": round(dt * 1e3, 2), "iterations": st.iterations, "rel_residual": st.rel_residual,
-                         "max_error_vs_exact": err}
-        res[f"{n}^3"] = out
+    res = {"workload": "biharmonic BVP, sin-product manufactured solution, 2-ring from the exact u, "
+                       "fast-Poisson preconditioned CG; 2D sizes are nodes per side, 3D unknowns per side"}
+    for dim, sizes in ((2, (257, 1025, 2049)), (3, (63, 127, 255))):
+        op = stencils.biharmonic(dim)
+        for n in sizes:
+            bvp = S.biharmonic_bvp(dim, n)
+            f = torch.from_numpy(bvp.f).to(dev)
+            g = torch.from_numpy(bvp.g).to(dev)
+            out = {}
+            for name, prec in (("f64", native.SC_PREC_F64), ("f32_ru", native.SC_PREC_F32_RU)):
+                u = torch.zeros_like(f)
+                native.solve_biharmonic(op, bvp.h, f, u, g=g, g_halo=bvp.halo, tol=1e-10, precision=prec,
+                                        precond=native.SC_PC_FASTPOISSON)
+                u.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = native.solve_biharmonic(op, bvp.h, f, u, g=g, g_halo=bvp.halo, tol=1e-10, precision=prec,
+                                             precond=native.SC_PC_FASTPOISSON)
+                dt = time.perf_counter() - t0
+                err = float((u.cpu() - torch.from_numpy(bvp.u)).abs().max())
+                out[name] = {"ms": round(dt * 1e3, 2), "iterations": st.iterations,
+                             "rel_residual": st.rel_residual, "max_error_vs_exact": err}
+            res[f"{n}^{dim}"] = out
+    # the plain-CG reference point at one 3D size
+    bvp = S.biharmonic_bvp(3, 63)
+    f = torch.from_numpy(bvp.f).to(dev)
+    g = torch.from_numpy(bvp.g).to(dev)
+    u = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = native.solve_biharmonic(stencils.biharmonic(3), bvp.h, f, u, g=g, g_halo=bvp.halo, tol=1e-10)
+    res["63^3_plain_cg_f64"] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), "iterations": st.iterations}
     return res
 
 
@@ -223,7 +247,7 @@ def serve_bench(native, torch, n_req: int):
     out = {"workload": (f"{n_req} requests: 60% 2D biharmonic BVPs, nodes log-uniform in "
                         f"{SERVE_BVP_NODES[0]}..{SERVE_BVP_NODES[1]}; 40% single 3D Cahn-Hilliard steps, "
                         f"side log-uniform in {SERVE_CH_SIDE[0]}..{SERVE_CH_SIDE[1]} (eps=4h, dt=0.1h^2, S=2); "
-                        "all to a 1e-10 true relative residual"),
+                        "all to a 1e-10 true relative residual; BVPs with fast-Poisson preconditioned CG"),
            "load_factor": SERVE_LOAD}
 
     def progress(msg):
@@ -240,7 +264,8 @@ def serve_bench(native, torch, n_req: int):
             f = torch.from_numpy(data.f).to(dev)
             gg = torch.from_numpy(data.g).to(dev)
             u = torch.zeros_like(f)
-            native.solve_biharmonic(ops["bvp"], data.h, f, u, g=gg, g_halo=data.halo, tol=1e-10)
+            native.solve_biharmonic(ops["bvp"], data.h, f, u, g=gg, g_halo=data.halo, tol=1e-10,
+                                    precond=native.SC_PC_FASTPOISSON)
         else:
             u0, prm = data
             u = torch.from_numpy(u0).to(dev)
@@ -252,7 +277,7 @@ def serve_bench(native, torch, n_req: int):
     def run_server(precision, arrivals):
         # precision: one sc_precision for every request, or a dict by kind
         per_kind = precision if isinstance(precision, dict) else {"bvp": precision, "ch": precision}
-        srv = native.Server(max_slots=SERVE_SLOTS, tol=1e-10)
+        srv = native.Server(max_slots=SERVE_SLOTS, tol=1e-10, precond=native.SC_PC_FASTPOISSON)
         try:
             t_base = None
             ids = []
@@ -358,9 +383,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-extras", action="store_true", help="only the timed apply (for profiling)")
-    ap.add_argument("--extras", default="solves,ch,bvp3d,varcoef,serve,cpu",
+    ap.add_argument("--extras", default="solves,ch,bvp,varcoef,serve,cpu",
                     help="comma-separated extras to run after the timed apply")
-    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run plain device copies of the same 4097^2 FP64 arrays (calibrates the "
                          "HBM byte counters against a kernel of known traffic)")
@@ -464,9 +489,9 @@ def main():
     if "varcoef" in extras:
         print("[bench] varcoef", file=sys.stderr, flush=True)
         result["varcoef"] = varcoef_bench(native, torch)
-    if "bvp3d" in extras:
-        print("[bench] bvp3d", file=sys.stderr, flush=True)
-        result["bvp3d"] = bvp3d_bench(native, torch)
+    if "bvp" in extras:
+        print("[bench] bvp", file=sys.stderr, flush=True)
+        result["bvp"] = bvp_pcg_bench(native, torch)
     if "serve" in extras:
         result["serve"] = serve_bench(native, torch, args.serve_requests)
     if "cpu" in extras:

@@ -236,7 +236,64 @@ __global__ void __launch_bounds__(kNT) pc_init_kernel(T* __restrict__ S, double*
   }
 }
 
+// Error-free transformations: a + b = s + e exactly (Knuth), a * b = p + e
+// exactly (one FMA).
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
+  p = a * b;
+  e = __builtin_fma(a, b, -p);
+}
+
+__global__ void __launch_bounds__(kNT)
+    resid_dd_kernel(const double* __restrict__ x, int64_t px, int64_t zx, const double* __restrict__ b,
+                    double* __restrict__ r, int64_t pr, int64_t zr, int64_t n0, int64_t n1, int64_t n2,
+                    const TapTable taps, DevScalars* s, int flag, double* partials) {
+  const RowRange rr = block_rows(n1 * n2);
+  double dot = 0.0;
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t k = rho / n1, j = rho - k * n1;
+    const int64_t ox = k * zx + j * px, orr = k * zr + j * pr;
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) {
+      double hi = 0.0, lo = 0.0;  // sum w x as hi + lo
+      for (int t = 0; t < taps.n; ++t) {
+        const double v = x[ox + i + taps.off[t][0] + taps.off[t][1] * px + taps.off[t][2] * zx];
+        double p, pe, sum, se;
+        two_prod(taps.w[t], v, p, pe);
+        two_sum(hi, p, sum, se);
+        hi = sum;
+        lo += pe + se;
+      }
+      double d, de;
+      two_sum(b[orr + i], -hi, d, de);
+      const double res = d + (de - lo);
+      r[orr + i] = res;
+      dot += res * res;
+    }
+  }
+  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s->ticket, [&](double total) {
+    s->rr_true = total;
+    if (flag) {
+      s->rr = total;
+      s->beta = 0.0;
+      s->done = (total <= s->rr_stop) ? 1 : 0;
+    }
+  });
+}
+
 }  // namespace
+
+hipError_t launch_resid_dd(const double* x, const Layout& lx, const double* b, double* r, const Layout& lr,
+                           const int64_t* n, const TapTable& taps, DevScalars* s, int flag, double* partials,
+                           hipStream_t st) {
+  const int nb = elem_blocks(n);
+  hipLaunchKernelGGL(resid_dd_kernel, dim3(nb), dim3(kNT), 0, st, x, lx.pitch, lx.zpitch, b, r, lr.pitch, lr.zpitch,
+                     n[0], n[1], n[2], taps, s, flag, partials);
+  return hipGetLastError();
+}
 
 hipError_t launch_pc_init(int dtype, void* S, double* lam, int64_t m, double h, hipStream_t st) {
   int64_t nb = (m * m + kNT - 1) / kNT;

@@ -292,6 +292,24 @@ KStencil to_box(const KStencil& ks) {
   return b;
 }
 
+TapTable tap_table(const KStencil& ks) {
+  TapTable t;
+  const int zr = ks.dim == 3 ? ks.R : 0;
+  for (int z = -zr; z <= zr; ++z)
+    for (int y = -ks.R; y <= ks.R; ++y)
+      for (int x = -ks.R; x <= ks.R; ++x) {
+        if (!in_pattern(ks.pat, ks.R, x, y, z)) continue;
+        const double w = ks.w[tap_index(ks.pat, ks.R, ks.dim, x, y, z)];
+        if (w == 0.0 || t.n >= kMaxTaps) continue;
+        t.off[t.n][0] = x;
+        t.off[t.n][1] = y;
+        t.off[t.n][2] = z;
+        t.w[t.n] = w;
+        ++t.n;
+      }
+  return t;
+}
+
 sc_status make_kstencil(const sc_stencil* s, double h, KStencil* out) {
   if (!s || !(h > 0.0) || !std::isfinite(h)) {
     set_error("invalid stencil or grid spacing");

@@ -135,6 +135,7 @@ class SolveTask {
   int stretch_idle_ = 0;       // blocks since it last halved
   bool fell_back_ = false;     // a mixed-precision solve that continued in FP64
   bool pc_ = false;            // preconditioned CG (BVP, fast-Poisson)
+  TapTable taps_;              // the operator's taps (double-double residual)
   FastPoisson pc64_, pc32_;
   Vec z64_, t64_, z32_, t32_;  // z = M^-1 r and its scratch, per precision
   sc_solve_stats stats_{};

@@ -183,3 +183,17 @@ def test_server_cancel_and_budget_on_device(nat, ops):
         assert res[0]["id"] == rid and res[0]["status"] == nat.SC_ENOMEM
     finally:
         srv.close()
+
+
+def test_server_preconditioned_alone_vs_mix(nat, ops):
+    # Preconditioned BVPs (library GEMMs on each request's stream) next to
+    # plain and CH requests: still bit-identical alone and in the mix.
+    jobs = _job_mix(nat, ops)
+    alone = [_serve(nat, [j], 1, precond=nat.SC_PC_FASTPOISSON)[0] for j in jobs]
+    mixed = _serve(nat, jobs, 16, precond=nat.SC_PC_FASTPOISSON)
+    for j, (ra, xa), (rm, xm) in zip(jobs, alone, mixed):
+        assert ra["status"] == nat.SC_OK and rm["status"] == nat.SC_OK
+        assert rm["iterations"] == ra["iterations"]
+        assert np.array_equal(xm, xa)
+        if j[0] == "bvp" and j[3] == nat.SC_PREC_F64:
+            assert ra["iterations"] <= 40
