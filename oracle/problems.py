@@ -17,6 +17,9 @@ statement of the problem:
 * ``ch_energy`` / ``mass``: the discrete free energy of Sec. 4.1 for the
   double well (u^2-1)^2/4 with gradient coefficient eps^2 (forward
   differences), and h^d sum u.
+* ``apply_extended`` / ``bvp_relres_extended``: the same apply and BVP
+  residual summed in x87 extended precision, for residual checks at grid
+  sizes where an FP64 sum rounds near the 1e-10 stopping tolerance.
 * ``flux_terms`` / ``varcoef_apply``: a composition with a varying
   coefficient between its factors (Sec. 2.2.3): y = sum_t B_t(M * A_t(x)),
   e.g. div(M grad(Lap f)) with A_a = D1_a o Lap and B_a = D1_a.
@@ -51,6 +54,44 @@ def true_relres(op: R.RStencil, x: np.ndarray, b: np.ndarray, mode: int, h: floa
     """||b - A x||_2 / ||b||_2, FP64, by the oracle's own apply."""
     r = b - capi.apply(op, x, mode, 0, h)
     return float(np.linalg.norm(r.ravel()) / np.linalg.norm(b.ravel()))
+
+
+def apply_extended(op: R.RStencil, x: np.ndarray, mode: int, halo: int = 0, h: float = 1.0) -> np.ndarray:
+    """y = (1/h^p) W x at the unknowns, summed in x87 extended precision.
+
+    The integer numerators multiply x in a 64-bit significand and the common
+    denominator and h^p divide once at the end, so a sum whose FP64 rounding
+    is large next to its value (a nearly converged residual of the
+    bi-Laplacian at fine h, where |W||x| ~ 1e15 |W x|) keeps about three
+    more digits. ``mode`` is ZERO_RING (x holds the unknowns) or HALO (x
+    carries a ring of width ``halo``)."""
+    if np.finfo(np.longdouble).nmant < 63:
+        raise RuntimeError("extended precision is not available on this host")
+    nums, den = op.integer_form()
+    dim = op.dim
+    xe = np.asarray(x, dtype=np.longdouble)
+    if mode == capi.ZERO_RING:
+        halo = op.radius()
+        xe = np.pad(xe, halo)
+    elif mode != capi.HALO:
+        raise ValueError("mode must be ZERO_RING or HALO")
+    shape = tuple(s - 2 * halo for s in xe.shape)
+    acc = np.zeros(shape, dtype=np.longdouble)
+    for off, num in sorted(nums.items()):
+        # offset component a runs along numpy axis dim-1-a (x is the last axis)
+        sl = tuple(slice(halo + off[dim - 1 - ax], halo + off[dim - 1 - ax] + shape[ax]) for ax in range(dim))
+        acc += np.longdouble(num) * xe[sl]
+    return acc / (np.longdouble(den) * np.longdouble(h) ** op.p)
+
+
+def bvp_relres_extended(op: R.RStencil, x: np.ndarray, f: np.ndarray, g: np.ndarray, halo: int,
+                        h: float) -> float:
+    """||b - A x||_2 / ||b||_2 with b = f - A_ring(g), all in extended precision."""
+    ring = np.array(g, dtype=np.longdouble, copy=True)
+    ring[tuple(slice(halo, s - halo) for s in ring.shape)] = 0
+    b = np.asarray(f, dtype=np.longdouble) - apply_extended(op, ring, capi.HALO, halo, h)
+    r = b - apply_extended(op, x, capi.ZERO_RING, 0, h)
+    return float(np.sqrt(np.sum(r * r)) / np.sqrt(np.sum(b * b)))
 
 
 def ch_operator(dim: int, h: float, eps: float, dt: float, S: float) -> R.RStencil:

@@ -253,7 +253,10 @@ def test_large_bvp_reaches_tolerance_with_compensated_residual(native):
     # here (|A||x| ~ 1e15 in the interior); the double-double residual lets
     # the preconditioned solve stop at the requested 1e-10. The solution is
     # checked against the manufactured u at the discretisation error O(h^2)
-    # (1.6e-7 at this h, from the 2nd-order rate pinned on small grids).
+    # (1.6e-7 at this h, from the 2nd-order rate pinned on small grids), and
+    # the oracle recomputes the residual with extended-precision sums.
     bvp, x, st = _gpu_bvp(native, 2, 2049, native.SC_PREC_F64, precond=native.SC_PC_FASTPOISSON)
     assert st.status == native.SC_OK and st.rel_residual <= 1e-10
     assert np.max(np.abs(x - bvp.u)) <= 2.5e-7
+    rel = OP.bvp_relres_extended(R.biharmonic(2), x, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert rel <= 1e-10, rel

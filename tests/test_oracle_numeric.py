@@ -6,6 +6,7 @@ the paper's stated convergence order, or conservation laws.
 """
 
 import math
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -111,6 +112,68 @@ def test_bvp_matches_dense_solve_17():
     M = R.assemble_dense(op, (bvp.n, bvp.n), False, bvp.h)
     ref = np.linalg.solve(M, b.ravel())
     np.testing.assert_allclose(x.ravel(), ref, rtol=1e-9)
+
+
+def _exact_zero_ring_apply(op, x):
+    # brute force in rational arithmetic: y_i = sum_k w_k x_{i+o_k}, zero outside
+    dim = op.dim
+    y = np.empty(x.shape, dtype=object)
+    for idx in np.ndindex(*x.shape):
+        acc = Fraction(0)
+        for off, w in op.weights.items():
+            j = tuple(idx[ax] + off[dim - 1 - ax] for ax in range(dim))
+            if all(0 <= j[ax] < x.shape[ax] for ax in range(dim)):
+                acc += w * Fraction(float(x[j]))
+        y[idx] = acc
+    return y
+
+
+@pytest.mark.parametrize("dim,fourth", [(2, False), (2, True), (3, False)])
+def test_extended_apply_pins(dim, fourth):
+    op = R.biharmonic(dim, fourth) if dim == 2 else R.biharmonic(3)
+    rad = op.radius()
+    nums, den = op.integer_form()
+    wsum = sum(abs(v) for v in nums.values())
+    shape = (7, 6, 5)[:dim]
+    # brute force: exact rational sums on a tiny grid
+    xr = S.uniform_field(shape, seed=43)
+    ex = _exact_zero_ring_apply(op, xr)
+    got = P.apply_extended(op, xr, capi.ZERO_RING)
+    err = max(abs(Fraction(float(g)) - e) for g, e in zip(got.ravel(), ex.ravel()))
+    assert err <= Fraction(1, 2 ** 50) * wsum / den
+    # integer inputs: the numerator sums are exact in both precisions
+    xi = S.integer_field(shape, seed=41)
+    ext = P.apply_extended(op, xi, capi.ZERO_RING)
+    assert np.array_equal(np.rint(ext * den), np.vectorize(lambda v: float(v * den))(_exact_zero_ring_apply(op, xi)))
+    if den == 1:
+        assert np.array_equal(ext.astype(np.float64), capi.apply(op, xi, capi.ZERO_RING))
+    # halo mode is the zero-ring apply of the unknowns plus the ring's part
+    xh = S.uniform_field(tuple(s + 2 * rad for s in shape), seed=44)
+    inner = tuple(slice(rad, s - rad) for s in xh.shape)
+    ring = xh.copy()
+    ring[inner] = 0.0
+    lhs = P.apply_extended(op, xh, capi.HALO, rad)
+    rhs = P.apply_extended(op, xh[inner], capi.ZERO_RING) + P.apply_extended(op, ring, capi.HALO, rad)
+    assert float(np.max(np.abs(lhs - rhs))) <= 2.0 ** -58 * wsum / den
+    # an exactly linear field with full 53-bit values (1 + c (2^-30 + 2^-52),
+    # c < 64) is annihilated; its products and partial sums need up to 66 bits
+    c = np.indices(tuple(s + 2 * rad for s in shape)).sum(axis=0).astype(np.float64)
+    lin = 1.0 + c * (2.0 ** -30 + 2.0 ** -52)
+    e_ext = float(np.max(np.abs(P.apply_extended(op, lin, capi.HALO, rad)))) * den
+    e_64 = float(np.max(np.abs(capi.apply(op, lin, capi.HALO, rad)))) * den
+    assert e_ext <= 2.0 ** -60 * wsum * 2
+    if max(abs(v) for v in nums.values()) <= 64:
+        assert e_ext == 0.0 and e_64 > 0.0
+
+
+def test_extended_residual_matches_fp64_where_fp64_is_accurate():
+    bvp = S.biharmonic_bvp(2, 33)
+    op = R.biharmonic(2)
+    x, it, rel, rc = P.bvp_solve(op, bvp.f, bvp.g, bvp.halo, bvp.h, tol=1e-8)
+    b = P.bvp_rhs(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    r64 = P.true_relres(op, x, b, capi.ZERO_RING, bvp.h)
+    rext = P.bvp_relres_extended(op, x, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert abs(rext - r64) <= 1e-6 * r64
 
 
 @pytest.mark.parametrize("N", [17, 33, 65])
