@@ -20,6 +20,8 @@ Also reported (measured outside the timed steps, same process):
 * "ch": Cahn-Hilliard steps at 1024^2 and 256^3;
 * "bvp": preconditioned BVP solves at 257..2049^2 and 63..255^3;
 * "varcoef": the variable-coefficient operator div(M grad(Lap x)) at 4097^2;
+* "csr": the assembled baseline (rocSPARSE CSR SpMV) against the matrix-free
+  sweep at 4097^2 (33 points) and 256^3 (25 points);
 * "serve": the request server against one-at-a-time solves on a Poisson
   stream of BVPs and CH steps.
 """
@@ -377,13 +379,67 @@ def varcoef_bench(native, torch, reps: int = 20):
             "note": "fused minimum = read x and M, write y (24 B/pt); the two-sweep form moves 11 words/pt"}
 
 
+def csr_bench(native, torch, mf_apply_ms: float, reps: int = 20):
+    """The assembled baseline: each operator as a CSR matrix multiplied by
+    rocSPARSE (row-split and adaptive), against the matrix-free sweep on the
+    same grid. 2D: the benchmark's 33-point operator on 4097^2 (the
+    matrix-free time is the timed apply's); 3D: the 25-point bi-Laplacian on
+    256^3, both forms timed here on contiguous arrays."""
+    import synthetic as S
+    from paper_2205_03354_amd import stencils
+
+    dev = torch.device("cuda:0")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"workload": "y = A x with A assembled as CSR (int64 row pointers, int32 columns, FP64 values), "
+                       "rocSPARSE SpMV; 4097^2 33-point periodic and 256^3 25-point periodic"}
+    for name, dim, side, mf_ms in (("4097^2_33pt", 2, N_GRID, mf_apply_ms), ("256^3_25pt", 3, 256, None)):
+        st = stencils.biharmonic(2, fourth_order=True) if dim == 2 else stencils.biharmonic(3)
+        shape = (side,) * dim
+        h = 1.0 / side
+        x = torch.from_numpy(S.uniform_field(shape, seed=0)).to(dev)
+        y = torch.empty_like(x)
+        if mf_ms is None:
+            mf_ms = timed(lambda: native.apply_composed(st, x, y, native.SC_BC_PERIODIC, h=h))
+        row = {"matrix_free_ms": round(mf_ms, 4)}
+        pts = float(side) ** dim
+        for alg_name, alg in (("rowsplit", native.SC_CSR_ROWSPLIT), ("adaptive", native.SC_CSR_ADAPTIVE)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            A = native.Csr(st, shape, native.SC_CSR_PERIODIC, h=h, alg=alg)
+            t_asm = time.perf_counter() - t0
+            ms = timed(lambda: A.spmv(x, y))
+            moved = A.bytes + 16.0 * pts
+            row[alg_name] = {"assemble_s": round(t_asm, 3), "spmv_ms": round(ms, 4),
+                             "gbs_algorithmic_16B_per_pt": round(16.0 * pts / ms / 1e6, 1),
+                             "gbs_moved": round(moved / ms / 1e6, 1),
+                             "matrix_free_speedup": round(ms / mf_ms, 2)}
+            row["nnz"] = A.nnz
+            row["csr_bytes"] = A.bytes
+            A.close()
+            del A
+        out[name] = row
+        print(f"[bench] csr {name}: {row}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-extras", action="store_true", help="only the timed apply (for profiling)")
-    ap.add_argument("--extras", default="solves,ch,bvp,varcoef,serve,cpu",
+    ap.add_argument("--extras", default="solves,ch,bvp,varcoef,csr,serve,cpu",
                     help="comma-separated extras to run after the timed apply")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-probe", action="store_true",
@@ -489,6 +545,9 @@ def main():
     if "varcoef" in extras:
         print("[bench] varcoef", file=sys.stderr, flush=True)
         result["varcoef"] = varcoef_bench(native, torch)
+    if "csr" in extras:
+        print("[bench] csr", file=sys.stderr, flush=True)
+        result["csr"] = csr_bench(native, torch, avg_kernel_ms)
     if "bvp" in extras:
         print("[bench] bvp", file=sys.stderr, flush=True)
         result["bvp"] = bvp_pcg_bench(native, torch)

@@ -383,6 +383,60 @@ sc_status sc_server_load(sc_server* s, int32_t* queued, int32_t* active, int32_t
 void sc_server_destroy(sc_server* s);
 
 /* ---------------------------------------------------------------------------
+ * Assembled operator (the baseline the matrix-free apply is measured against)
+ * ------------------------------------------------------------------------- */
+
+typedef struct sc_csr sc_csr;
+
+/* Which values the assembled rows reach: SC_CSR_PERIODIC wraps indices
+ * modulo n (taps that alias to one column on grids narrower than the stencil
+ * are summed into one entry); SC_CSR_ZERO_RING drops taps that leave the
+ * grid, which is the operator of Krylov vectors with a zero ring (the BVP
+ * matrix A of Sec. 3.3). */
+typedef enum sc_csr_bc { SC_CSR_PERIODIC = 0, SC_CSR_ZERO_RING = 1 } sc_csr_bc;
+/* rocSPARSE's CSR SpMV algorithm: row-split (no analysis, deterministic) or
+ * adaptive (an analysis pass at the first product). */
+typedef enum sc_csr_alg { SC_CSR_ROWSPLIT = 0, SC_CSR_ADAPTIVE = 1 } sc_csr_alg;
+
+/*
+ * Assemble stencil `s` on an n[0] x n[1] (x n[2]) grid of unknowns as a CSR
+ * matrix in device memory, the assembled form in which the paper builds its
+ * composed operators (Sec. 4.5-4.6; Table 3 counts its non-zeros, e.g. 13 per
+ * row for the 13-point bi-Laplacian on a periodic grid). Row i = x + n0 (y +
+ * n1 z) holds, for every tap t, the weight num_t/(den h^p) (rounded once, to
+ * double and then to `dtype`, as in sc_apply_composed) in the column of grid
+ * point (x, y, z) + u_t. Columns ascend within each row. Row pointers are
+ * int64 (rows + 1 of them), column indices int32, so the grid must hold fewer
+ * than 2^31 points; at most 128 taps. dim is 2 or 3 and equals the
+ * stencil's; n[2] must be 1 in 2D. bc is an sc_csr_bc, dtype an sc_dtype,
+ * alg an sc_csr_alg. Assembly runs on the current device on `stream` and the
+ * call returns once it has completed. The library owns the matrix: release
+ * it with sc_csr_free. Errors: SC_EINVAL, SC_EUNSUPPORTED (taps),
+ * SC_ENOMEM, SC_EDEVICE.
+ */
+sc_status sc_csr_assemble(const sc_stencil* s, double h, int32_t dim, const int64_t* n, int32_t bc,
+                          int32_t dtype, int32_t alg, sc_stream_t stream, sc_csr** out);
+/* Rows, stored entries and device bytes of the three CSR arrays; NULL
+ * outputs are skipped. */
+sc_status sc_csr_info(const sc_csr* m, int64_t* rows, int64_t* nnz, uint64_t* bytes);
+/*
+ * y = A x by rocSPARSE on `stream`. x and y match the matrix's grid and
+ * dtype, with halo 0 and contiguous storage (pitch[0] == n[0], and in 3D
+ * pitch[1] == n[0] n[1]); y must not overlap x; the current device must be
+ * the matrix's. The first product on a matrix also sizes and allocates the
+ * library's SpMV workspace and runs its analysis (blocking); later products
+ * are asynchronous. Calls on one matrix must not run concurrently from
+ * several threads. Errors: SC_EINVAL, SC_ENOMEM, SC_EDEVICE.
+ */
+sc_status sc_csr_spmv(sc_csr* m, const sc_grid* x, sc_grid* y, sc_stream_t stream);
+/* Copy the CSR arrays to caller-owned host buffers (rows + 1 int64 row
+ * pointers, nnz int32 columns, nnz values of the matrix's dtype); NULL
+ * buffers are skipped. Synchronous. */
+sc_status sc_csr_export(const sc_csr* m, int64_t* row_ptr, int32_t* col, void* val);
+/* Wait for the device, then release the matrix (NULL is ignored). */
+void sc_csr_free(sc_csr* m);
+
+/* ---------------------------------------------------------------------------
  * Errors and version
  * ------------------------------------------------------------------------- */
 

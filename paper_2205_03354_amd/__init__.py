@@ -8,8 +8,13 @@ The public calls mirror the C ABI in ``include/scomp.h``:
 
 from ._native import (  # noqa: F401
     ApplyPlan,
+    Csr,
     SC_BC_HALO,
     SC_BC_PERIODIC,
+    SC_CSR_ADAPTIVE,
+    SC_CSR_PERIODIC,
+    SC_CSR_ROWSPLIT,
+    SC_CSR_ZERO_RING,
     SC_PC_FASTPOISSON,
     SC_PC_NONE,
     SC_PREC_F32_IR,

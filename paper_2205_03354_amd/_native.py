@@ -23,13 +23,16 @@ SC_PC_NONE, SC_PC_FASTPOISSON = 0, 1
 SC_F64, SC_F32 = 0, 1
 SC_BC_PERIODIC, SC_BC_HALO = 0, 1
 SC_PREC_F64, SC_PREC_F32_IR, SC_PREC_F32_RU = 0, 1, 2
+SC_CSR_PERIODIC, SC_CSR_ZERO_RING = 0, 1
+SC_CSR_ROWSPLIT, SC_CSR_ADAPTIVE = 0, 1
 
 EXPORTED = (
     "sc_stencil_create", "sc_compose_stencil", "sc_stencil_lincomb", "sc_stencil_get",
     "sc_stencil_radius", "sc_stencil_free", "sc_apply_composed", "sc_apply_varcoef", "sc_solve_opts_default",
     "sc_solve_biharmonic", "sc_ch_step", "sc_grid_diagnostics", "sc_status_str",
     "sc_last_error", "sc_version", "sc_server_create", "sc_server_submit", "sc_server_poll",
-    "sc_server_cancel", "sc_server_load", "sc_server_destroy",
+    "sc_server_cancel", "sc_server_load", "sc_server_destroy", "sc_csr_assemble", "sc_csr_info",
+    "sc_csr_spmv", "sc_csr_export", "sc_csr_free",
 )
 
 
@@ -112,6 +115,14 @@ def _load() -> ctypes.CDLL:
     L.sc_server_destroy.argtypes = [P]
     L.sc_server_destroy.restype = None
     for name in ("sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_cancel", "sc_server_load"):
+        getattr(L, name).restype = ctypes.c_int
+    L.sc_csr_assemble.argtypes = [P, D, I32, P, I32, I32, I32, P, PP]
+    L.sc_csr_info.argtypes = [P, P, P, P]
+    L.sc_csr_spmv.argtypes = [P, ctypes.POINTER(SCGrid), ctypes.POINTER(SCGrid), P]
+    L.sc_csr_export.argtypes = [P, P, P, P]
+    L.sc_csr_free.argtypes = [P]
+    L.sc_csr_free.restype = None
+    for name in ("sc_csr_assemble", "sc_csr_info", "sc_csr_spmv", "sc_csr_export"):
         getattr(L, name).restype = ctypes.c_int
     L.sc_status_str.argtypes = [ctypes.c_int]
     L.sc_status_str.restype = ctypes.c_char_p
@@ -286,6 +297,56 @@ class ApplyPlan:
 
 
 @dataclass
+class Csr:
+    """The stencil assembled as a CSR matrix on the device (sc_csr_assemble);
+    ``spmv(x, y)`` is y = A x by rocSPARSE on contiguous grids without a ring."""
+
+    def __init__(self, st: Stencil, shape, bc: int = SC_CSR_PERIODIC, h: float = 1.0, dtype=None,
+                 alg: int = SC_CSR_ROWSPLIT, stream=None):
+        import torch
+
+        dtype = torch.float64 if dtype is None else dtype
+        self.dtype = dtype
+        self.shape = tuple(int(s) for s in shape)
+        dim = len(self.shape)
+        n = (ctypes.c_int64 * 3)(*(list(self.shape[::-1]) + [1] * (3 - dim)))
+        self._h = ctypes.c_void_p()
+        dt = SC_F64 if dtype == torch.float64 else SC_F32
+        _check(lib.sc_csr_assemble(st.handle, float(h), dim, n, int(bc), dt, int(alg), _stream(stream),
+                                   ctypes.byref(self._h)))
+        rows, nnz, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
+        _check(lib.sc_csr_info(self._h, ctypes.byref(rows), ctypes.byref(nnz), ctypes.byref(nb)))
+        self.rows, self.nnz, self.bytes = rows.value, nnz.value, nb.value
+
+    def spmv(self, x, y, stream=None):
+        gx, gy = grid_of(x), grid_of(y)
+        _check(lib.sc_csr_spmv(self._h, ctypes.byref(gx), ctypes.byref(gy), _stream(stream)))
+        return y
+
+    def export(self):
+        """(row_ptr int64, col int32, val) as numpy arrays."""
+        import numpy as np
+
+        rp = np.empty(self.rows + 1, dtype=np.int64)
+        col = np.empty(self.nnz, dtype=np.int32)
+        import torch
+
+        val = np.empty(self.nnz, dtype=np.float64 if self.dtype == torch.float64 else np.float32)
+        _check(lib.sc_csr_export(self._h, rp.ctypes.data, col.ctypes.data, val.ctypes.data))
+        return rp, col, val
+
+    def close(self):
+        if self._h:
+            lib.sc_csr_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class SolveStats:
     iterations: int
     outer: int

@@ -44,7 +44,7 @@ def _units():
     units = []
     for name in ("abi.cpp", "stencil.cpp", "solver.cpp", "server.cpp", "precond.cpp"):
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name + ".o"), ["-x", "hip"]))
-    for name in ("launch_host.hip", "elementwise.hip"):
+    for name in ("launch_host.hip", "elementwise.hip", "csr.hip"):
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name + ".o"), []))
     for part in range(NPARTS):
         units.append((os.path.join(CSRC, "dispatch.hip"), os.path.join(BUILD, f"dispatch_{part}.o"),
@@ -75,7 +75,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + "\n".join(r[1] for r in failed))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + [u[1] for u in units] + \
-        ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+        ["-L/opt/rocm/lib", "-lrocblas", "-lrocsparse", "-Wl,-rpath,/opt/rocm/lib"]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stderr)

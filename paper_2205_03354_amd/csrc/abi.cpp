@@ -103,6 +103,30 @@ sc_status sc_apply_varcoef(int32_t nterms, const sc_stencil* const* inner, const
   SC_GUARD(return sc::apply_varcoef(nterms, inner, outer, h, mob, in, out, bc, reinterpret_cast<hipStream_t>(stream));)
 }
 
+sc_status sc_csr_assemble(const sc_stencil* s, double h, int32_t dim, const int64_t* n, int32_t bc,
+                          int32_t dtype, int32_t alg, sc_stream_t stream, sc_csr** out) {
+  SC_GUARD(return sc::csr_assemble(s, h, dim, n, bc, dtype, alg, reinterpret_cast<hipStream_t>(stream), out);)
+}
+
+sc_status sc_csr_info(const sc_csr* m, int64_t* rows, int64_t* nnz, uint64_t* bytes) {
+  SC_GUARD(return sc::csr_info(m, rows, nnz, bytes);)
+}
+
+sc_status sc_csr_spmv(sc_csr* m, const sc_grid* x, sc_grid* y, sc_stream_t stream) {
+  SC_GUARD(return sc::csr_spmv(m, x, y, reinterpret_cast<hipStream_t>(stream));)
+}
+
+sc_status sc_csr_export(const sc_csr* m, int64_t* row_ptr, int32_t* col, void* val) {
+  SC_GUARD(return sc::csr_export(m, row_ptr, col, val);)
+}
+
+void sc_csr_free(sc_csr* m) {
+  try {
+    sc::csr_free(m);
+  } catch (...) {
+  }
+}
+
 void sc_solve_opts_default(sc_solve_opts* o) {
   if (!o) return;
   o->tol = 1e-10;

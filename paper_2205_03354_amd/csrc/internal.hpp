@@ -212,5 +212,14 @@ sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* 
 // driver before process exit).
 void* pool_alloc(size_t bytes);
 void pool_free(void* p);
+size_t esize(int dtype);
+
+// Assembled CSR form of a stencil (csr.hip).
+sc_status csr_assemble(const sc_stencil* s, double h, int32_t dim, const int64_t* n, int32_t bc, int32_t dtype,
+                       int32_t alg, hipStream_t st, sc_csr** out);
+sc_status csr_info(const sc_csr* m, int64_t* rows, int64_t* nnz, uint64_t* bytes);
+sc_status csr_spmv(sc_csr* m, const sc_grid* x, sc_grid* y, hipStream_t st);
+sc_status csr_export(const sc_csr* m, int64_t* row_ptr, int32_t* col, void* val);
+void csr_free(sc_csr* m);
 
 }  // namespace sc

@@ -54,9 +54,9 @@ void pool_free(void* p) {
   g_free.insert({it->second, p});
 }
 
-namespace {
-
 size_t esize(int dtype) { return dtype == SC_F64 ? 8 : 4; }
+
+namespace {
 
 SweepLaunch sweep_on(int kind, const KStencil& ks, bool periodic, int dtype, const int64_t* n) {
   SweepLaunch L;

@@ -149,3 +149,24 @@ def test_apply_validation_without_gpu(native):
     g.pitch[0] = 4
     rc = native.lib.sc_apply_composed(lap.handle, 1.0, ctypes.byref(g), ctypes.byref(o), 0, None)
     assert rc == native.SC_EINVAL and b"pitch" in native.lib.sc_last_error()
+
+
+def test_csr_argument_validation(native):
+    # rejected before any device work, so this runs without a GPU
+    import ctypes
+
+    st = _lib_stencil(native, R.biharmonic(2))
+    out = ctypes.c_void_p()
+    n = (ctypes.c_int64 * 3)(8, 8, 1)
+    L = native.lib
+    assert L.sc_csr_assemble(st.handle, 1.0, 2, n, 5, native.SC_F64, 0, None, ctypes.byref(out)) == native.SC_EINVAL
+    assert L.sc_csr_assemble(st.handle, 1.0, 2, n, 0, 7, 0, None, ctypes.byref(out)) == native.SC_EINVAL
+    assert L.sc_csr_assemble(st.handle, 1.0, 2, n, 0, native.SC_F64, 9, None, ctypes.byref(out)) == native.SC_EINVAL
+    assert L.sc_csr_assemble(st.handle, 1.0, 3, n, 0, native.SC_F64, 0, None, ctypes.byref(out)) == native.SC_EINVAL
+    assert L.sc_csr_assemble(st.handle, -1.0, 2, n, 0, native.SC_F64, 0, None, ctypes.byref(out)) == native.SC_EINVAL
+    big = (ctypes.c_int64 * 3)(1 << 16, 1 << 15, 1)
+    assert L.sc_csr_assemble(st.handle, 1.0, 2, big, 0, native.SC_F64, 0, None, ctypes.byref(out)) == native.SC_EINVAL
+    assert "2^31" in L.sc_last_error().decode()
+    assert not out.value
+    assert L.sc_csr_info(None, None, None, None) == native.SC_EINVAL
+    L.sc_csr_free(None)
