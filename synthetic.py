@@ -109,3 +109,24 @@ def periodic_cos_mode(shape, kvec) -> np.ndarray:
     for a in range(dim):
         phase = phase + 2.0 * math.pi * kvec[dim - 1 - a] * grids[a] / shape[a]
     return np.cos(phase)
+
+
+def spinodal_initial(dim: int, n: int, h: float = 1.0, c0: float = 0.5, amp: float = 0.01) -> np.ndarray:
+    """Initial concentration of the spinodal-decomposition benchmark (Sec. 4.1):
+    c0 plus amp times a sum of three cosine products, sampled at x_i = i h,
+    i = 0 .. n-1, on every axis (the 200^2 and 64^3 unit domains are n = 200 and
+    n = 64 with h = 1). Arrays are (y, x) or (z, y, x)."""
+    c = np.arange(n, dtype=np.float64) * h
+    if dim == 2:
+        Y, X = np.meshgrid(c, c, indexing="ij")
+        s = (np.cos(0.105 * X) * np.cos(0.11 * Y)
+             + (np.cos(0.13 * X) * np.cos(0.087 * Y)) ** 2
+             + np.cos(0.025 * X - 0.15 * Y) * np.cos(0.07 * X - 0.02 * Y))
+    elif dim == 3:
+        Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+        s = (np.cos(0.105 * X) * np.cos(0.11 * Y) * np.cos(0.11 * Z)
+             + (np.cos(0.13 * X) * np.cos(0.087 * Y) * np.cos(0.1 * Z)) ** 2
+             + np.cos(0.025 * X - 0.15 * Y - 0.1 * Z) * np.cos(0.07 * X - 0.02 * Y + 0.01 * Z))
+    else:
+        raise ValueError("dim must be 2 or 3")
+    return c0 + amp * s
