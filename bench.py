@@ -20,6 +20,8 @@ Also reported (measured outside the timed steps, same process):
 * "ch": Cahn-Hilliard steps at 1024^2 and 256^3;
 * "bvp": preconditioned BVP solves at 257..2049^2 and 63..255^3;
 * "varcoef": the variable-coefficient operator div(M grad(Lap x)) at 4097^2;
+* "spinodal": the paper's spinodal-decomposition benchmark with IMEX steps
+  of orders 1-3 (time per step, free energy, temporal convergence);
 * "csr": the assembled baseline (rocSPARSE CSR SpMV) against the matrix-free
   sweep at 4097^2 (33 points) and 256^3 (25 points);
 * "serve": the request server against one-at-a-time solves on a Poisson
@@ -379,6 +381,62 @@ def varcoef_bench(native, torch, reps: int = 20):
             "note": "fused minimum = read x and M, write y (24 B/pt); the two-sweep form moves 11 words/pt"}
 
 
+def spinodal_bench(native, torch):
+    """The spinodal-decomposition benchmark of Sec. 4 (M = 5, kappa = 2,
+    rho = 5, wells 0.3 / 0.7, h = 1, the cosine initial condition): time per
+    IMEX step on the paper's 200^2 (dt 0.05) and 64^3 (dt 0.25) domains and on
+    larger domains, and the temporal-convergence study (final time 10, errors
+    against a third-order run with dt = 1/1024 in 2D and 1/512 in 3D)."""
+    import math
+
+    import synthetic as S
+    from paper_2205_03354_amd import stencils
+
+    dev = torch.device("cuda:0")
+    out = {"workload": "spinodal decomposition (Sec. 4.1), periodic, h = 1, M = 5, kappa = 2, rho = 5, "
+                       "c_alpha = 0.3, c_beta = 0.7, cosine initial condition; IMEX RK orders 1-3 (ARS pairs), "
+                       "stage solves to 1e-10"}
+
+    def run(dim, n, dt, order, steps, tol=1e-10):
+        c = torch.from_numpy(S.spinodal_initial(dim, n)).to(dev)
+        prm = native.spinodal_params(dt=dt, order=order)
+        st = native.spinodal_steps(stencils.laplacian(dim), c, prm, steps, tol=tol)
+        return c, st, prm
+
+    for dim, n, dt, steps in ((2, 200, 0.05, 200), (3, 64, 0.25, 40), (2, 2048, 0.05, 20), (3, 256, 0.25, 8)):
+        row = {}
+        for order in (1, 2, 3):
+            run(dim, n, dt, order, 2)  # warm-up
+            c, st, prm = run(dim, n, dt, order, steps)
+            m, e = native.spinodal_energy(c, prm)
+            row[f"order{order}"] = {"ms_per_step": round(1e3 * st.seconds / steps, 3),
+                                    "cg_iterations_per_step": round(st.iterations / steps, 1),
+                                    "t_final": round(dt * steps, 3), "free_energy": e}
+        out[f"{n}^{dim}_dt{dt}"] = row
+        print(f"[bench] spinodal {n}^{dim}: {row}", file=sys.stderr, flush=True)
+
+    # errors below about 1e-7 at t = 10 reach the floor set by the stage
+    # tolerance, amplified by the growth of the unstable spinodal modes
+    CONV_STEPS = (40, 80, 160, 320, 640)
+    conv = {}
+    for dim, n, ref_m, orders in ((2, 200, 10240, (1, 2, 3)), (3, 64, 5120, (1, 2, 3))):
+        ref, _, _ = run(dim, n, 10.0 / ref_m, 3, ref_m, tol=1e-13)
+        ref = ref.cpu().numpy()
+        res = {}
+        for order in orders:
+            errs = []
+            for m in CONV_STEPS:
+                c, _, _ = run(dim, n, 10.0 / m, order, m, tol=1e-13)
+                errs.append(float(abs(c.cpu().numpy() - ref).max()))
+            res[f"order{order}"] = {"dt": [10.0 / m for m in CONV_STEPS], "max_error": errs,
+                                    "observed_order": [round(math.log2(errs[i] / errs[i + 1]), 3)
+                                                       for i in range(len(errs) - 1)]}
+        conv[f"{n}^{dim}"] = res
+        print(f"[bench] spinodal convergence {n}^{dim}: {res}", file=sys.stderr, flush=True)
+    out["temporal_convergence_t10"] = conv
+    return out
+
+
 def csr_bench(native, torch, mf_apply_ms: float, reps: int = 20):
     """The assembled baseline: each operator as a CSR matrix multiplied by
     rocSPARSE (row-split and adaptive), against the matrix-free sweep on the
@@ -439,7 +497,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-extras", action="store_true", help="only the timed apply (for profiling)")
-    ap.add_argument("--extras", default="solves,ch,bvp,varcoef,csr,serve,cpu",
+    ap.add_argument("--extras", default="solves,ch,bvp,varcoef,csr,spinodal,serve,cpu",
                     help="comma-separated extras to run after the timed apply")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--copy-probe", action="store_true",
@@ -548,6 +606,9 @@ def main():
     if "csr" in extras:
         print("[bench] csr", file=sys.stderr, flush=True)
         result["csr"] = csr_bench(native, torch, avg_kernel_ms)
+    if "spinodal" in extras:
+        print("[bench] spinodal", file=sys.stderr, flush=True)
+        result["spinodal"] = spinodal_bench(native, torch)
     if "bvp" in extras:
         print("[bench] bvp", file=sys.stderr, flush=True)
         result["bvp"] = bvp_pcg_bench(native, torch)

@@ -383,6 +383,59 @@ sc_status sc_server_load(sc_server* s, int32_t* queued, int32_t* active, int32_t
 void sc_server_destroy(sc_server* s);
 
 /* ---------------------------------------------------------------------------
+ * The spinodal-decomposition benchmark (Sec. 4) with IMEX time stepping
+ * ------------------------------------------------------------------------- */
+
+/* c_t = div(M grad(f'(c) - kappa Lap c)), f(c) = rho (c - c_alpha)^2 (c - c_beta)^2
+ * (Sec. 4.1, eq. (cahn); the benchmark uses M = 5, kappa = 2, rho = 5,
+ * c_alpha = 0.3, c_beta = 0.7, h = 1). */
+typedef struct sc_spinodal_params {
+  double h;         /* grid spacing */
+  double dt;        /* time step */
+  double mobility;  /* M (constant) */
+  double kappa;     /* gradient energy coefficient */
+  double rho;       /* height of the double well */
+  double c_alpha;   /* the double well's minima */
+  double c_beta;
+  int32_t order;    /* IMEX order: 1, 2 or 3 */
+} sc_spinodal_params;
+
+typedef struct sc_spinodal_stats {
+  int64_t steps;
+  int64_t solves;           /* implicit stage solves */
+  int64_t iterations;       /* CG iterations over all stage solves */
+  double max_rel_residual;  /* largest true relative residual a stage solve ended with */
+  double seconds;
+} sc_spinodal_stats;
+
+/*
+ * Advance c by `nsteps` IMEX Runge-Kutta steps on a periodic grid. The
+ * linear fourth-order part K(c) = -M kappa (L o L) c is implicit and the
+ * non-linear part N(c) = M L f'(c) explicit, as in Sec. 4.1; L is `lap`
+ * (the second-order 5- or 7-point Laplacian, p = 2, or in 2D a radius-2
+ * cross Laplacian) and L o L its exact composition. Orders 1, 2 and 3 are
+ * the L-stable, stiffly accurate pairs of Ascher, Ruuth and Spiteri (1997):
+ * forward/backward Euler, ARS(2,2,2) and ARS(4,4,3); each implicit stage is
+ * a CG solve of (I + dt a_ii M kappa L o L) Y_i = (explicit terms), started
+ * from the previous stage, to opts->tol (true relative residual) in the
+ * precision opts->precision (fast-Poisson preconditioning does not apply;
+ * opts->precond must be SC_PC_NONE). c is FP64, any halo (the ring is not
+ * touched), updated in place. Blocking: returns after the last step.
+ * Errors: SC_EINVAL, SC_EUNSUPPORTED, SC_ENOMEM, SC_EDEVICE, SC_ENOTCONV /
+ * SC_EBREAKDOWN from a stage (c then holds the last completed step).
+ */
+sc_status sc_spinodal_steps(const sc_stencil* lap, const sc_spinodal_params* p, int32_t nsteps,
+                            const sc_solve_opts* opts, sc_grid* c, sc_spinodal_stats* stats,
+                            sc_stream_t stream);
+/*
+ * Mass h^d sum c and the free energy of Sec. 4.1,
+ * F = h^d sum [rho (c - c_alpha)^2 (c - c_beta)^2 + (kappa / 2) |grad c|^2]
+ * with forward differences on the periodic grid (c FP64). Blocking.
+ */
+sc_status sc_spinodal_energy(const sc_grid* c, const sc_spinodal_params* p, double* mass, double* energy,
+                             sc_stream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Assembled operator (the baseline the matrix-free apply is measured against)
  * ------------------------------------------------------------------------- */
 

@@ -33,6 +33,9 @@ from ._native import (  # noqa: F401
     grid_diagnostics,
     grid_of,
     solve_biharmonic,
+    spinodal_energy,
+    spinodal_params,
+    spinodal_steps,
     stencil_lincomb,
     version,
 )

@@ -31,7 +31,8 @@ EXPORTED = (
     "sc_stencil_radius", "sc_stencil_free", "sc_apply_composed", "sc_apply_varcoef", "sc_solve_opts_default",
     "sc_solve_biharmonic", "sc_ch_step", "sc_grid_diagnostics", "sc_status_str",
     "sc_last_error", "sc_version", "sc_server_create", "sc_server_submit", "sc_server_poll",
-    "sc_server_cancel", "sc_server_load", "sc_server_destroy", "sc_csr_assemble", "sc_csr_info",
+    "sc_server_cancel", "sc_server_load", "sc_server_destroy", "sc_spinodal_steps", "sc_spinodal_energy",
+    "sc_csr_assemble", "sc_csr_info",
     "sc_csr_spmv", "sc_csr_export", "sc_csr_free",
 )
 
@@ -56,6 +57,17 @@ class SCSolveOpts(ctypes.Structure):
 class SCSolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("outer", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class SCSpinodalParams(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("dt", ctypes.c_double), ("mobility", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("rho", ctypes.c_double), ("c_alpha", ctypes.c_double),
+                ("c_beta", ctypes.c_double), ("order", ctypes.c_int32)]
+
+
+class SCSpinodalStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("solves", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("max_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
 class SCChParams(ctypes.Structure):
@@ -116,6 +128,11 @@ def _load() -> ctypes.CDLL:
     L.sc_server_destroy.restype = None
     for name in ("sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_cancel", "sc_server_load"):
         getattr(L, name).restype = ctypes.c_int
+    L.sc_spinodal_steps.argtypes = [P, ctypes.POINTER(SCSpinodalParams), I32, ctypes.POINTER(SCSolveOpts),
+                                    ctypes.POINTER(SCGrid), ctypes.POINTER(SCSpinodalStats), P]
+    L.sc_spinodal_energy.argtypes = [ctypes.POINTER(SCGrid), ctypes.POINTER(SCSpinodalParams), P, P, P]
+    L.sc_spinodal_steps.restype = ctypes.c_int
+    L.sc_spinodal_energy.restype = ctypes.c_int
     L.sc_csr_assemble.argtypes = [P, D, I32, P, I32, I32, I32, P, PP]
     L.sc_csr_info.argtypes = [P, P, P, P]
     L.sc_csr_spmv.argtypes = [P, ctypes.POINTER(SCGrid), ctypes.POINTER(SCGrid), P]
@@ -296,7 +313,6 @@ class ApplyPlan:
             _check(rc)
 
 
-@dataclass
 class Csr:
     """The stencil assembled as a CSR matrix on the device (sc_csr_assemble);
     ``spmv(x, y)`` is y = A x by rocSPARSE on contiguous grids without a ring."""
@@ -347,6 +363,7 @@ class Csr:
             pass
 
 
+@dataclass
 class SolveStats:
     iterations: int
     outer: int
@@ -403,6 +420,48 @@ def ch_step(lap: Stencil, u, h: float, eps: float, dt: float, S: float, tol: flo
     if raise_on_error:
         _check(status)
     return _stats(st, status)
+
+
+@dataclass
+class SpinodalStats:
+    steps: int
+    solves: int
+    iterations: int
+    max_rel_residual: float
+    seconds: float
+    status: int
+
+
+def spinodal_params(h: float = 1.0, dt: float = 0.05, mobility: float = 5.0, kappa: float = 2.0,
+                    rho: float = 5.0, c_alpha: float = 0.3, c_beta: float = 0.7, order: int = 1) -> SCSpinodalParams:
+    """Parameters of the spinodal-decomposition benchmark (defaults: the
+    benchmark's M, kappa, rho and well minima on h = 1)."""
+    return SCSpinodalParams(h, dt, mobility, kappa, rho, c_alpha, c_beta, int(order))
+
+
+def spinodal_steps(lap: Stencil, c, params: SCSpinodalParams, nsteps: int, tol: float = 1e-10,
+                   max_iter: int = 10**6, precision: int = SC_PREC_F64, inner_tol: float = 0.0,
+                   check_every: int = 16, use_graph: bool = True, raise_on_error: bool = True,
+                   halo: int = 0, stream=None) -> SpinodalStats:
+    """Advance c (FP64, periodic) by nsteps IMEX steps in place (sc_spinodal_steps)."""
+    gc = grid_of(c, halo)
+    o = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph)
+    st = SCSpinodalStats()
+    status = lib.sc_spinodal_steps(lap.handle, ctypes.byref(params), int(nsteps), ctypes.byref(o), ctypes.byref(gc),
+                                   ctypes.byref(st), _stream(stream))
+    if raise_on_error:
+        _check(status)
+    return SpinodalStats(int(st.steps), int(st.solves), int(st.iterations), float(st.max_rel_residual),
+                         float(st.seconds), status)
+
+
+def spinodal_energy(c, params: SCSpinodalParams, halo: int = 0, stream=None) -> Tuple[float, float]:
+    """(mass, free energy) of c (sc_spinodal_energy)."""
+    gc = grid_of(c, halo)
+    m, e = ctypes.c_double(), ctypes.c_double()
+    _check(lib.sc_spinodal_energy(ctypes.byref(gc), ctypes.byref(params), ctypes.byref(m), ctypes.byref(e),
+                                  _stream(stream)))
+    return m.value, e.value
 
 
 def grid_diagnostics(u, h: float, eps: float, stream=None) -> Tuple[float, float]:

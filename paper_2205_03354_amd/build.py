@@ -42,7 +42,7 @@ def _jobs():
 
 def _units():
     units = []
-    for name in ("abi.cpp", "stencil.cpp", "solver.cpp", "server.cpp", "precond.cpp"):
+    for name in ("abi.cpp", "stencil.cpp", "solver.cpp", "server.cpp", "precond.cpp", "imex.cpp"):
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name + ".o"), ["-x", "hip"]))
     for name in ("launch_host.hip", "elementwise.hip", "csr.hip"):
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name + ".o"), []))

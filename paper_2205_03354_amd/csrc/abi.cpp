@@ -103,6 +103,17 @@ sc_status sc_apply_varcoef(int32_t nterms, const sc_stencil* const* inner, const
   SC_GUARD(return sc::apply_varcoef(nterms, inner, outer, h, mob, in, out, bc, reinterpret_cast<hipStream_t>(stream));)
 }
 
+sc_status sc_spinodal_steps(const sc_stencil* lap, const sc_spinodal_params* p, int32_t nsteps,
+                            const sc_solve_opts* opts, sc_grid* c, sc_spinodal_stats* stats,
+                            sc_stream_t stream) {
+  SC_GUARD(return sc::spinodal_steps(lap, p, nsteps, opts, c, stats, reinterpret_cast<hipStream_t>(stream));)
+}
+
+sc_status sc_spinodal_energy(const sc_grid* c, const sc_spinodal_params* p, double* mass, double* energy,
+                             sc_stream_t stream) {
+  SC_GUARD(return sc::spinodal_energy(c, p, mass, energy, reinterpret_cast<hipStream_t>(stream));)
+}
+
 sc_status sc_csr_assemble(const sc_stencil* s, double h, int32_t dim, const int64_t* n, int32_t bc,
                           int32_t dtype, int32_t alg, sc_stream_t stream, sc_csr** out) {
   SC_GUARD(return sc::csr_assemble(s, h, dim, n, bc, dtype, alg, reinterpret_cast<hipStream_t>(stream), out);)

@@ -74,7 +74,7 @@ enum SweepKind : int {
   K_CGDIR = 1,    // p = r + beta p_old ; q = S p ; <p, q>  -> alpha
   K_RESID = 2,    // r = b - S x ; <r, r>                   -> rr_true (and a CG (re)start)
   K_BVPRHS = 3,   // b = f - S g_ring ; <b, b>              -> bb, rr_stop
-  K_CHRHS = 4,    // rhs = u + dt S(u^3 - (1+S0) u) ; <rhs, rhs> -> bb, rr_stop
+  K_CHRHS = 4,    // rhs = c3 u + c0 S(u^3 - c1 u) ; <rhs, rhs> -> bb, rr_stop
   K_SCALE = 5,    // out = aux * S in   (pointwise coefficient after a stencil)
   K_ACCUM = 6     // out = aux + S in   (aux may be out itself: accumulate)
 };

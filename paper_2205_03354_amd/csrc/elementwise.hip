@@ -113,10 +113,63 @@ __global__ void __launch_bounds__(kNT)
   }
 }
 
+// dst = src + add (layouts may differ)
+__global__ void __launch_bounds__(kNT)
+    copy_shift_kernel(const double* __restrict__ src, int64_t sp, int64_t sz, double* __restrict__ dst,
+                      int64_t dp, int64_t dz, int64_t n0, int64_t n1, int64_t n2, double add) {
+  const RowRange rr = block_rows(n1 * n2);
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t os = row_offset(rho, n1, sp, sz);
+    const int64_t od = row_offset(rho, n1, dp, dz);
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) dst[od + i] = src[os + i] + add;
+  }
+}
+
+// dst = src; <src, src> -> bb, rr_stop = tol2 bb (a given right-hand side)
+__global__ void __launch_bounds__(kNT)
+    copy_norm_kernel(const double* __restrict__ src, int64_t sp, int64_t sz, double* __restrict__ dst,
+                     int64_t dp, int64_t dz, int64_t n0, int64_t n1, int64_t n2, DevScalars* s, double tol2,
+                     double* partials) {
+  const RowRange rr = block_rows(n1 * n2);
+  double dot = 0.0;
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t os = row_offset(rho, n1, sp, sz);
+    const int64_t od = row_offset(rho, n1, dp, dz);
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) {
+      const double v = src[os + i];
+      dst[od + i] = v;
+      dot += v * v;
+    }
+  }
+  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s->ticket, [&](double total) {
+    s->bb = total;
+    s->rr_stop = tol2 * total;
+  });
+}
+
+// out = base + sum_k coef_k v_k, all in one layout (k in increasing order)
+__global__ void __launch_bounds__(kNT)
+    combine_kernel(CombineTerms t, const double* base, double* out, int64_t pitch,
+                   int64_t zpitch, int64_t n0, int64_t n1, int64_t n2) {
+  const RowRange rr = block_rows(n1 * n2);
+  for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
+    const int64_t o = row_offset(rho, n1, pitch, zpitch);
+    for (int64_t i = threadIdx.x; i < n0; i += kNT) {
+      double acc = base[o + i];
+      for (int k = 0; k < t.n; ++k) acc = __builtin_fma(t.coef[k], t.v[k][o + i], acc);
+      out[o + i] = acc;
+    }
+  }
+}
+
+// Sums for the free energy: WELL = false, u + the scaled double well
+// (u^2 - 1)^2 / 4; WELL = true, (u - wa)^2 (u - wb)^2. Also sum u and the
+// squared forward differences (periodic).
+template <bool WELL>
 __global__ void __launch_bounds__(kNT)
     diagnostics_kernel(const double* __restrict__ u, int64_t pitch, int64_t zpitch, int dim,
                        int64_t n0, int64_t n1, int64_t n2, double* partials, unsigned int* ticket,
-                       double* out3) {
+                       double* out3, double wa, double wb) {
   const RowRange rr = block_rows(n1 * n2);
   double m = 0.0, bulk = 0.0, grad = 0.0;
   for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
@@ -136,9 +189,14 @@ __global__ void __launch_bounds__(kNT)
         const double dz = u[oz + i] - v;
         g += dz * dz;
       }
-      const double w = v * v - 1.0;
       m += v;
-      bulk += 0.25 * w * w;
+      if constexpr (WELL) {
+        const double w = (v - wa) * (v - wb);
+        bulk += w * w;
+      } else {
+        const double w = v * v - 1.0;
+        bulk += 0.25 * w * w;
+      }
       grad += g;
     }
   }
@@ -374,10 +432,39 @@ hipError_t launch_copy(const double* src, int64_t sp, int64_t sz, double* dst, i
 
 hipError_t launch_diagnostics(const double* u, int64_t pitch, int64_t zpitch, int dim,
                               const int64_t* n, double* partials, unsigned int* ticket, double* out3,
-                              hipStream_t st) {
+                              hipStream_t st, const double* well) {
   const int nb = elem_blocks(n);
-  hipLaunchKernelGGL(diagnostics_kernel, dim3(nb), dim3(kNT), 0, st, u, pitch, zpitch, dim, n[0], n[1],
-                     n[2], partials, ticket, out3);
+  if (well)
+    hipLaunchKernelGGL(diagnostics_kernel<true>, dim3(nb), dim3(kNT), 0, st, u, pitch, zpitch, dim, n[0], n[1],
+                       n[2], partials, ticket, out3, well[0], well[1]);
+  else
+    hipLaunchKernelGGL(diagnostics_kernel<false>, dim3(nb), dim3(kNT), 0, st, u, pitch, zpitch, dim, n[0], n[1],
+                       n[2], partials, ticket, out3, 0.0, 0.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_shift(const double* src, int64_t sp, int64_t sz, double* dst, int64_t dp, int64_t dz,
+                             const int64_t* n, double add, hipStream_t st) {
+  const int nb = elem_blocks(n);
+  hipLaunchKernelGGL(copy_shift_kernel, dim3(nb), dim3(kNT), 0, st, src, sp, sz, dst, dp, dz, n[0], n[1], n[2],
+                     add);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_norm(const double* src, int64_t sp, int64_t sz, double* dst, int64_t dp, int64_t dz,
+                            const int64_t* n, DevScalars* s, double tol2, double* partials, hipStream_t st) {
+  const int nb = elem_blocks(n);
+  hipLaunchKernelGGL(copy_norm_kernel, dim3(nb), dim3(kNT), 0, st, src, sp, sz, dst, dp, dz, n[0], n[1], n[2], s,
+                     tol2, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineTerms& t, const double* base, double* out, const Layout& lay,
+                          const int64_t* n, hipStream_t st) {
+  if (t.n < 0 || t.n > kMaxCombine) return hipErrorInvalidValue;
+  const int nb = elem_blocks(n);
+  hipLaunchKernelGGL(combine_kernel, dim3(nb), dim3(kNT), 0, st, t, base, out, lay.pitch, lay.zpitch, n[0], n[1],
+                     n[2]);
   return hipGetLastError();
 }
 

@@ -89,6 +89,7 @@ struct SweepLaunch {
   DevScalars* scal = nullptr;
   double* partials = nullptr;
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  double c3 = 1.0;  // K_CHRHS: weight of the centre value
   int flag = 0;
   bool vec_store = false;
   bool in_aligned = false;  // in / in2 / aux rows start on 16-byte boundaries
@@ -173,8 +174,23 @@ hipError_t launch_copy(const double* src, int64_t sp, int64_t sz, double* dst, i
 // mass = sum u, grad = sum_axes (u_{i+e} - u_i)^2, bulk = sum (u^2-1)^2/4,
 // periodic; results into out[3] (device) via a deterministic reduction.
 hipError_t launch_diagnostics(const double* u, int64_t pitch, int64_t zpitch, int dim,
-                              const int64_t* n, double* partials, unsigned int* ticket,
-                              double* out3, hipStream_t st);
+                              const int64_t* n, double* partials, unsigned int* ticket, double* out3,
+                              hipStream_t st, const double* well = nullptr);
+// dst = src + add over the interior (FP64, layouts may differ).
+hipError_t launch_copy_shift(const double* src, int64_t sp, int64_t sz, double* dst, int64_t dp, int64_t dz,
+                             const int64_t* n, double add, hipStream_t st);
+// dst = src; s->bb = <src, src>, s->rr_stop = tol2 s->bb.
+hipError_t launch_copy_norm(const double* src, int64_t sp, int64_t sz, double* dst, int64_t dp, int64_t dz,
+                            const int64_t* n, DevScalars* s, double tol2, double* partials, hipStream_t st);
+// out = base + sum_k coef[k] v[k] (FP64, one layout; out may alias base).
+constexpr int kMaxCombine = 10;
+struct CombineTerms {
+  int n = 0;
+  const double* v[kMaxCombine] = {};
+  double coef[kMaxCombine] = {};
+};
+hipError_t launch_combine(const CombineTerms& t, const double* base, double* out, const Layout& lay,
+                          const int64_t* n, hipStream_t st);
 
 // ------------------------------------------------------ entry-point bodies
 sc_status stencil_create(int32_t dim, int32_t npts, const int32_t* offsets, const int64_t* num,
@@ -213,6 +229,12 @@ sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* 
 void* pool_alloc(size_t bytes);
 void pool_free(void* p);
 size_t esize(int dtype);
+
+// IMEX steps of the spinodal-decomposition benchmark (imex.cpp).
+sc_status spinodal_steps(const sc_stencil* lap, const sc_spinodal_params* p, int32_t nsteps,
+                         const sc_solve_opts* opts, sc_grid* c, sc_spinodal_stats* stats, hipStream_t st);
+sc_status spinodal_energy(const sc_grid* c, const sc_spinodal_params* p, double* mass, double* energy,
+                          hipStream_t st);
 
 // Assembled CSR form of a stencil (csr.hip).
 sc_status csr_assemble(const sc_stencil* s, double h, int32_t dim, const int64_t* n, int32_t bc, int32_t dtype,

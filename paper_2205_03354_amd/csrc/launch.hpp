@@ -55,7 +55,7 @@ SweepArgs<T> make_args(const SweepLaunch& L) {
   a.n0 = L.n[0]; a.n1 = L.n[1]; a.n2 = L.n[2];
   a.scal = L.scal;
   a.partials = L.partials;
-  a.c0 = L.c0; a.c1 = L.c1; a.c2 = L.c2;
+  a.c0 = L.c0; a.c1 = L.c1; a.c2 = L.c2; a.c3 = L.c3;
   a.flag = L.flag;
   a.vec_store = L.vec_store ? 1 : 0;
   a.in_aligned = L.in_aligned ? 1 : 0;

@@ -56,8 +56,6 @@ void pool_free(void* p) {
 
 size_t esize(int dtype) { return dtype == SC_F64 ? 8 : 4; }
 
-namespace {
-
 SweepLaunch sweep_on(int kind, const KStencil& ks, bool periodic, int dtype, const int64_t* n) {
   SweepLaunch L;
   L.kind = kind;
@@ -70,7 +68,7 @@ SweepLaunch sweep_on(int kind, const KStencil& ks, bool periodic, int dtype, con
   return L;
 }
 
-bool aligned16(const void* p, int64_t pitch, int64_t zpitch, int64_t es, bool three_d) {
+static bool aligned16(const void* p, int64_t pitch, int64_t zpitch, int64_t es, bool three_d) {
   if (!p) return true;
   return (uintptr_t)p % 16 == 0 && (pitch * es) % 16 == 0 && (!three_d || (zpitch * es) % 16 == 0);
 }
@@ -90,7 +88,6 @@ sc_status launch(SweepLaunch L, hipStream_t st) {
   }
   return SC_OK;
 }
-
 
 // Rows are padded so that the sweeps' 16-byte chunk DMAs of a strip
 // (64 x 16 bytes plus halo chunks) stay inside the row even where the strip
@@ -119,6 +116,8 @@ size_t vec_bytes(int dim, const int64_t* n, int halo, int dtype) {
   const size_t raw = (size_t)(lay.zpitch * planes) * esize(dtype) + 256;
   return (raw + 4095) & ~(size_t)4095;
 }
+
+namespace {
 
 int partial_slots(const TaskSpec& sp) {
   int slots = kElemBlocks;
@@ -212,7 +211,7 @@ sc_status SolveTask::make(Vec* v, int dtype) {
 sc_status SolveTask::init(const TaskSpec& spec, hipStream_t st) {
   spec_ = spec;
   st_ = st;
-  periodic_ = spec.kind == TASK_CH;
+  periodic_ = spec.kind == TASK_CH || spec.kind == TASK_LIN;
   f32_ = spec.o.precision != SC_PREC_F64;
   ru_ = spec.o.precision == SC_PREC_F32_RU;
   restart_ = true;
@@ -433,6 +432,11 @@ sc_status SolveTask::start(const GridView& u0, const GridView& f, const GridView
     const GridView& gv = g ? *g : zero;
     s = sweep(K_BVPRHS, SC_F64, spec_.ksA, nullptr, nullptr, nullptr, nullptr, b_.base, nullptr, b_.lay, 0, 0, 0,
               tol2, d64_, &gv, &f);
+  } else if (spec_.kind == TASK_LIN) {
+    // the given right-hand side and its norm
+    SC_HIP_CHECK(launch_copy_norm(f.p, f.pitch, f.zpitch, (double*)b_.base, b_.lay.pitch, b_.lay.zpitch, spec_.n,
+                                  d64_, tol2, partials_, st_));
+    s = SC_OK;
   } else {
     // rhs = u + dt L(u^3 - (1+S) u), from x0 = u
     s = sweep(K_CHRHS, SC_F64, spec_.ksL, x_.base, &x_.lay, nullptr, nullptr, b_.base, nullptr, b_.lay, 0,
@@ -451,6 +455,34 @@ sc_status SolveTask::start(const GridView& u0, const GridView& f, const GridView
   if ((s = enqueue_residual(0)) != SC_OK) return s;
   phase_ = P_OUTER;
   return enqueue_read(true);
+}
+
+sc_status SolveTask::restart(const GridView& u0, const GridView& f) {
+  if (spec_.kind != TASK_LIN || !d64_) {
+    set_error("only an initialised linear-solve task can be restarted");
+    return SC_EINVAL;
+  }
+  // a mixed-precision task that fell back to FP64 keeps solving in FP64
+  f32_ = spec_.o.precision != SC_PREC_F64 && !fell_back_;
+  ru_ = f32_ && spec_.o.precision == SC_PREC_F32_RU;
+  restart_ = true;
+  cur_ = 0;
+  block_cur0_ = 0;
+  block_iter0_ = 0;
+  pending_ = SC_OK;
+  status_ = SC_OK;
+  outer_ = 0;
+  stalled_ = 0;
+  best_ = 0.0;
+  inner_start_ = 0;
+  inner_keep_ = 0;
+  stretch_best_ = 0.0;
+  stretch_idle_ = 0;
+  stats_ = sc_solve_stats{};
+  SC_HIP_CHECK(hipMemsetAsync(dev_block_, 0, 2 * sizeof(DevScalars), st_));
+  std::memset(h64_, 0, 2 * sizeof(DevScalars));
+  phase_ = P_NONE;
+  return start(u0, f, nullptr);
 }
 
 void SolveTask::finish(sc_status s) {
@@ -647,7 +679,7 @@ void* interior(const sc_grid* g) {
   return static_cast<char*>(g->data) + off * es;
 }
 
-static GridView view_of(const sc_grid* g) {
+GridView view_of(const sc_grid* g) {
   return GridView{static_cast<const double*>(interior(g)), g->pitch[0], g->pitch[1]};
 }
 
@@ -843,17 +875,15 @@ sc_status check_opts(const sc_solve_opts& o) {
 
 // The operator of one Cahn-Hilliard step, I + dt eps^2 L o L - dt S L,
 // composed exactly and combined once in extended precision.
-sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* ksA, KStencil* ksL) {
+sc_status lap_operator(const sc_stencil* lap, long double cI, long double cLL, long double cL, KStencil* out) {
   sc_status r;
   sc_stencil* LL = nullptr;
   if ((r = compose(lap, lap, &LL)) != SC_OK) return r;
   std::map<std::array<int32_t, 3>, long double> wa;
-  const long double h = prm->h;
-  const long double cLL = (long double)prm->dt * prm->eps * prm->eps / (h * h * h * h);
-  const long double cL = -(long double)prm->dt * prm->S / (h * h);
-  wa[{0, 0, 0}] += 1.0L;
+  if (cI != 0.0L) wa[{0, 0, 0}] += cI;
   for (size_t t = 0; t < LL->num.size(); ++t) wa[LL->off[t]] += cLL * (long double)LL->num[t] / LL->den;
-  for (size_t t = 0; t < lap->num.size(); ++t) wa[lap->off[t]] += cL * (long double)lap->num[t] / lap->den;
+  if (cL != 0.0L)
+    for (size_t t = 0; t < lap->num.size(); ++t) wa[lap->off[t]] += cL * (long double)lap->num[t] / lap->den;
   delete LL;
   std::vector<std::array<int32_t, 3>> offs;
   std::vector<long double> ws;
@@ -861,7 +891,15 @@ sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* 
     offs.push_back(kv.first);
     ws.push_back(kv.second);
   }
-  if ((r = make_kstencil(lap->dim, offs, ws, ksA)) != SC_OK) return r;
+  return make_kstencil(lap->dim, offs, ws, out);
+}
+
+sc_status ch_operator(const sc_stencil* lap, const sc_ch_params* prm, KStencil* ksA, KStencil* ksL) {
+  sc_status r;
+  const long double h = prm->h;
+  const long double cLL = (long double)prm->dt * prm->eps * prm->eps / (h * h * h * h);
+  const long double cL = -(long double)prm->dt * prm->S / (h * h);
+  if ((r = lap_operator(lap, 1.0L, cLL, cL, ksA)) != SC_OK) return r;
   return make_kstencil(lap, prm->h, ksL);
 }
 
@@ -887,7 +925,7 @@ sc_status check_ch(const sc_stencil* lap, const sc_ch_params* prm, int dim) {
 // per-thread, per-device non-blocking stream that first waits for the work
 // already queued on the null stream; the call returns only after that stream
 // has drained, so later null-stream work is ordered after it.
-static sc_status blocking_stream(hipStream_t caller, hipStream_t* out) {
+sc_status blocking_stream(hipStream_t caller, hipStream_t* out) {
   *out = caller;
   if (caller) return SC_OK;
   struct Cached {
@@ -908,7 +946,7 @@ static sc_status blocking_stream(hipStream_t caller, hipStream_t* out) {
   return SC_OK;
 }
 
-static sc_status run_blocking(SolveTask& t) {
+sc_status run_blocking(SolveTask& t) {
   bool done = false;
   while (!done) {
     SC_HIP_CHECK(hipStreamSynchronize(t.stream()));

@@ -62,6 +62,7 @@ struct SweepArgs {
   DevScalars* scal;
   double* partials;
   double c0, c1, c2;      // K_CHRHS: dt, 1+S; K_BVPRHS/K_CHRHS: c2 = tol^2
+  double c3;              // K_CHRHS: weight of the centre value u
   int flag;               // K_RESID: 1 = also (re)start the CG recurrence
 };
 
@@ -324,7 +325,7 @@ __global__ void __launch_bounds__(64)
       }
     } else if constexpr (KIND == K_CHRHS) {
 #pragma unroll
-      for (int v = 0; v < VPL; ++v) res[v] = cenv[v] + (T)a.c0 * accv[v];
+      for (int v = 0; v < VPL; ++v) res[v] = __builtin_fma((T)a.c0, accv[v], (T)a.c3 * cenv[v]);
     }
     if constexpr (HAS_DOT) {
 #pragma unroll

@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(NT)
           } else if constexpr (KIND == K_ACCUM) {
             a.out[gz * a.zout + gy * a.pout + col] = a.aux[gz * a.zaux + gy * a.paux + col] + accv[v];
           } else if constexpr (KIND == K_CHRHS) {
-            const T rr = a.in[gz * a.zin + gy * a.pin + col] + (T)a.c0 * accv[v];
+            const T rr = __builtin_fma((T)a.c0, accv[v], (T)a.c3 * a.in[gz * a.zin + gy * a.pin + col]);
             a.out[gz * a.zout + gy * a.pout + col] = rr;
             dot += (double)rr * (double)rr;
           }

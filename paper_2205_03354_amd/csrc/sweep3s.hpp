@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(64)
       }
     } else if constexpr (KIND == K_CHRHS) {
 #pragma unroll
-      for (int v = 0; v < VPL; ++v) res[v] = cenv[v] + (T)a.c0 * accv[v];
+      for (int v = 0; v < VPL; ++v) res[v] = __builtin_fma((T)a.c0, accv[v], (T)a.c3 * cenv[v]);
     }
     if constexpr (HAS_DOT) {
 #pragma unroll

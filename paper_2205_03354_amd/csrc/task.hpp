@@ -14,7 +14,10 @@
 
 namespace sc {
 
-enum TaskKind : int { TASK_BVP = 0, TASK_CH = 1 };
+// TASK_BVP: ring-mode biharmonic BVP (b from f and the ring values);
+// TASK_CH: periodic Cahn-Hilliard step (b from u); TASK_LIN: periodic
+// solve of A x = b for a given b (the stages of an IMEX step).
+enum TaskKind : int { TASK_BVP = 0, TASK_CH = 1, TASK_LIN = 2 };
 
 // A read-only FP64 grid view: `p` addresses interior element (0,0,0).
 struct GridView {
@@ -73,6 +76,9 @@ class SolveTask {
   // x0 := u0; right-hand side (BVP: f - A g_ring, g may be null; CH: from
   // x0); first true residual; scalars to the host.
   sc_status start(const GridView& u0, const GridView& f, const GridView* g);
+  // TASK_LIN: solve again with a new x0 and right-hand side f, reusing the
+  // workspace and the captured graphs (the previous solve has finished).
+  sc_status restart(const GridView& u0, const GridView& f);
   // The previously enqueued chunk has completed: decide, enqueue the next
   // chunk. *done = true when the solve has finished (see status()).
   sc_status advance(bool* done);
@@ -140,6 +146,21 @@ class SolveTask {
   Vec z64_, t64_, z32_, t32_;  // z = M^-1 r and its scratch, per precision
   sc_solve_stats stats_{};
 };
+
+// A grid's interior as a view; the stream a blocking call runs on (a
+// library stream ordered after the NULL stream when the caller passes it);
+// drive a started task to completion on its stream.
+GridView view_of(const sc_grid* g);
+sc_status blocking_stream(hipStream_t caller, hipStream_t* out);
+sc_status run_blocking(SolveTask& t);
+// cI I + cLL (L o L) + cL L with L = lap's weights as given (no h scaling).
+sc_status lap_operator(const sc_stencil* lap, long double cI, long double cLL, long double cL, KStencil* out);
+size_t vec_bytes(int dim, const int64_t* n, int halo, int dtype);
+// A sweep descriptor for n with no buffers yet; launch one after deriving
+// its alignment flags (SC_EUNSUPPORTED when no kernel instance fits).
+SweepLaunch sweep_on(int kind, const KStencil& ks, bool periodic, int dtype, const int64_t* n);
+sc_status launch(SweepLaunch L, hipStream_t st);
+Layout make_layout(int dim, const int64_t* n, int halo, int dtype);
 
 // Pinned host slots for scalar read-back (one pair per live task).
 DevScalars* pinned_pair_alloc();

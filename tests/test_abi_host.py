@@ -170,3 +170,13 @@ def test_csr_argument_validation(native):
     assert not out.value
     assert L.sc_csr_info(None, None, None, None) == native.SC_EINVAL
     L.sc_csr_free(None)
+
+
+def test_binding_result_records(native):
+    s = native.SolveStats(3, 1, 1e-11, 2.0, 0.5, 0)
+    assert s.iterations == 3 and s.rel_residual == 1e-11
+    t = native.SpinodalStats(2, 8, 40, 1e-12, 0.1, 0)
+    assert t.solves == 8 and t.iterations == 40
+    p = native.spinodal_params(dt=0.25, order=3)
+    assert (p.h, p.dt, p.mobility, p.kappa, p.rho, p.c_alpha, p.c_beta, p.order) == (1.0, 0.25, 5.0, 2.0, 5.0, 0.3,
+                                                                                         0.7, 3)
