@@ -96,9 +96,8 @@ struct Taps {
   T w[N];
 };
 
-// Device scalars of one Krylov solve. One reduction kernel at a time uses
-// `ticket` (kernels of one solve are serialised on its stream); the last
-// block resets it to 0, so no host-side clearing is needed between launches.
+// Device scalars of one Krylov solve, written only by the one-block finish
+// kernels (kernels of one solve are serialised on its stream).
 struct alignas(64) DevScalars {
   double rr;        // <r, r> of the current recurrence residual
   double pq;        // <p, A p>
@@ -110,7 +109,7 @@ struct alignas(64) DevScalars {
   double scale;     // refinement scale s = ||r||
   long long iter;   // iterations performed
   int done;         // 0 running, 1 recurrence converged, 2 breakdown
-  unsigned int ticket;
+  unsigned int unused;
   double rz;        // preconditioned CG: <r, M^-1 r>
   double pad[4];
 };
@@ -163,33 +162,46 @@ __device__ __forceinline__ double block_sum(double v) {
   }
 }
 
-// Single-pass deterministic grid reduction. Every block contributes `v`
-// (its partial sum, any thread's value is summed over the block) under the
-// index `slot` (the logical tile, fixed by the data it covers, not by the
-// scheduling order). The last block to arrive sums all partials in index
-// order and calls fin(total) from thread 0. Returns nothing; finalisers
-// write their results into DevScalars.
-template <int NT, typename Fin>
-__device__ __forceinline__ void grid_reduce(double v, int slot, int nslots, double* partials,
-                                            unsigned int* ticket, Fin&& fin) {
-  __shared__ int is_last;
+// Deterministic two-kernel grid reduction. The reducing kernel stores one
+// partial sum per block under `slot` (the logical tile, fixed by the data it
+// covers, not by the scheduling order); a one-block finish kernel launched
+// after it on the same stream (the kernel boundary makes the partials
+// visible) sums them in slot order and finalises into DevScalars. A
+// single-pass scheme where the last block to arrive finishes needs a
+// device-scope release per block, and those serialise: about 25 ns per block
+// on this part, 20-100 us for the grids here.
+template <int NT>
+__device__ __forceinline__ void block_partial(double v, int slot, double* partials) {
   const double bs = block_sum<NT>(v);
-  if (threadIdx.x == 0) {
-    partials[slot] = bs;
-    const unsigned int prev =
-        __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == (unsigned int)nslots - 1u);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nslots; i += NT) s += __hip_atomic_load(partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const double total = block_sum<NT>(s);
-  if (threadIdx.x == 0) {
-    fin(total);
-    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) partials[slot] = bs;
 }
+
+// Sum of partials[0 .. n) in a fixed order; valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double* partials, int n) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) s += partials[i];
+  return block_sum<NT>(s);
+}
+
+// What the finish kernel does with the total.
+enum FinKind : int {
+  FIN_CGDIR = 0,   // pq; alpha = (flag ? rz : rr) / pq, breakdown check
+  FIN_RESID = 1,   // rr_true (flag: also restart the recurrence: rr, beta, done)
+  FIN_RHS = 2,     // bb; rr_stop = c bb
+  FIN_UPDATE = 3,  // iteration count, convergence, beta, rr
+  FIN_IR = 4,      // FP32 stretch start (flag: keep the direction); c = inner tol^2
+  FIN_PCDOT = 5    // rz; beta = rz / rz_old (flag: restart, beta = 0)
+};
+
+struct FinArgs {
+  DevScalars* s = nullptr;
+  const DevScalars* s64 = nullptr;  // FIN_IR: the FP64 scalars (rr_true)
+  const double* partials = nullptr;
+  int n = 0;           // partial slots
+  double c = 0.0;
+  int flag = 0;
+  int skip_if_done = 0;  // the reducing kernel returned early once s->done was set
+};
 
 }  // namespace sc

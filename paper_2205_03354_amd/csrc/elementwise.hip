@@ -44,14 +44,7 @@ __global__ void __launch_bounds__(kNT)
       dot += (double)rv * (double)rv;
     }
   }
-  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s->ticket, [&](double total) {
-    s->iter += 1;
-    if (total <= s->rr_stop) {
-      s->done = 1;
-    }
-    s->beta = total / s->rr;
-    s->rr = total;
-  });
+  block_partial<kNT>(dot, (int)blockIdx.x, partials);
 }
 
 __global__ void __launch_bounds__(kNT)
@@ -74,19 +67,7 @@ __global__ void __launch_bounds__(kNT)
       dot += (double)v * (double)v;
     }
   }
-  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s32->ticket, [&](double total) {
-    if (keep_direction) {
-      // beta = <r', r'> / <r_old, r_old> with r' the replaced residual;
-      // the last update left beta = rr / rr_old and rr.
-      s32->beta = s32->rr > 0.0 ? s32->beta * (total / s32->rr) : 0.0;
-    } else {
-      s32->scale = sqrt(s64->rr_true);
-      s32->beta = 0.0;
-    }
-    s32->rr = total;
-    s32->rr_stop = inner_tol2 * total;
-    s32->done = total > 0.0 ? 0 : 1;
-  });
+  block_partial<kNT>(dot, (int)blockIdx.x, partials);
 }
 
 __global__ void __launch_bounds__(kNT)
@@ -141,10 +122,7 @@ __global__ void __launch_bounds__(kNT)
       dot += v * v;
     }
   }
-  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s->ticket, [&](double total) {
-    s->bb = total;
-    s->rr_stop = tol2 * total;
-  });
+  block_partial<kNT>(dot, (int)blockIdx.x, partials);
 }
 
 // out = base + sum_k coef_k v_k, all in one layout (k in increasing order)
@@ -267,11 +245,7 @@ __global__ void __launch_bounds__(kNT)
     const int64_t o = row_offset(rho, n1, pitch, zpitch);
     for (int64_t i = threadIdx.x; i < n0; i += kNT) dot += (double)r[o + i] * (double)z[o + i];
   }
-  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s->ticket, [&](double total) {
-    s->beta = (start || !(s->rz > 0.0)) ? 0.0 : total / s->rz;
-    s->rz = total;
-    if (!(total > 0.0)) s->done = 2;  // the preconditioner lost positivity
-  });
+  block_partial<kNT>(dot, (int)blockIdx.x, partials);
 }
 
 // S[j][k] = sqrt(2/(m+1)) sin(pi (j+1)(k+1)/(m+1)), the angle reduced
@@ -332,14 +306,87 @@ __global__ void __launch_bounds__(kNT)
       dot += res * res;
     }
   }
-  grid_reduce<kNT>(dot, (int)blockIdx.x, (int)gridDim.x, partials, &s->ticket, [&](double total) {
+  block_partial<kNT>(dot, (int)blockIdx.x, partials);
+}
+
+// Second half of every grid reduction here and in the sweeps (one block):
+// the total of the partials, in slot order, finalised into DevScalars.
+template <int FK>
+__global__ void __launch_bounds__(kNT) finish_kernel(FinArgs f) {
+  DevScalars* s = f.s;
+  if (f.skip_if_done && s->done) return;
+  const double total = sum_partials<kNT>(f.partials, f.n);
+  if (threadIdx.x != 0) return;
+  if constexpr (FK == FIN_CGDIR) {
+    s->pq = total;
+    if (!(total > 0.0) || !__builtin_isfinite(total))
+      s->done = 2;
+    else
+      s->alpha = (f.flag ? s->rz : s->rr) / total;  // flag: preconditioned, alpha = <r, z> / <p, A p>
+  } else if constexpr (FK == FIN_RESID) {
     s->rr_true = total;
-    if (flag) {
+    if (f.flag) {
       s->rr = total;
       s->beta = 0.0;
       s->done = (total <= s->rr_stop) ? 1 : 0;
     }
-  });
+  } else if constexpr (FK == FIN_RHS) {
+    s->bb = total;
+    s->rr_stop = f.c * total;
+  } else if constexpr (FK == FIN_UPDATE) {
+    s->iter += 1;
+    if (total <= s->rr_stop) s->done = 1;
+    s->beta = total / s->rr;
+    s->rr = total;
+  } else if constexpr (FK == FIN_IR) {
+    if (f.flag) {
+      // beta = <r', r'> / <r_old, r_old> with r' the replaced residual;
+      // the last update left beta = rr / rr_old and rr.
+      s->beta = s->rr > 0.0 ? s->beta * (total / s->rr) : 0.0;
+    } else {
+      s->scale = sqrt(f.s64->rr_true);
+      s->beta = 0.0;
+    }
+    s->rr = total;
+    s->rr_stop = f.c * total;
+    s->done = total > 0.0 ? 0 : 1;
+  } else if constexpr (FK == FIN_PCDOT) {
+    s->beta = (f.flag || !(s->rz > 0.0)) ? 0.0 : total / s->rz;
+    s->rz = total;
+    if (!(total > 0.0)) s->done = 2;  // the preconditioner lost positivity
+  }
+}
+
+}  // namespace
+
+hipError_t launch_finish(int fk, const FinArgs& f, hipStream_t st) {
+  switch (fk) {
+    case FIN_CGDIR: hipLaunchKernelGGL(finish_kernel<FIN_CGDIR>, dim3(1), dim3(kNT), 0, st, f); break;
+    case FIN_RESID: hipLaunchKernelGGL(finish_kernel<FIN_RESID>, dim3(1), dim3(kNT), 0, st, f); break;
+    case FIN_RHS: hipLaunchKernelGGL(finish_kernel<FIN_RHS>, dim3(1), dim3(kNT), 0, st, f); break;
+    case FIN_UPDATE: hipLaunchKernelGGL(finish_kernel<FIN_UPDATE>, dim3(1), dim3(kNT), 0, st, f); break;
+    case FIN_IR: hipLaunchKernelGGL(finish_kernel<FIN_IR>, dim3(1), dim3(kNT), 0, st, f); break;
+    case FIN_PCDOT: hipLaunchKernelGGL(finish_kernel<FIN_PCDOT>, dim3(1), dim3(kNT), 0, st, f); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+namespace {
+
+hipError_t finish(int fk, DevScalars* s, const double* partials, int n, double c, int flag, int skip,
+                  hipStream_t st, const DevScalars* s64 = nullptr) {
+  const hipError_t e = hipGetLastError();  // the reducing kernel's launch
+  if (e != hipSuccess) return e;
+  FinArgs f;
+  f.s = s;
+  f.s64 = s64;
+  f.partials = partials;
+  f.n = n;
+  f.c = c;
+  f.flag = flag;
+  f.skip_if_done = skip;
+  return launch_finish(fk, f, st);
 }
 
 }  // namespace
@@ -350,7 +397,7 @@ hipError_t launch_resid_dd(const double* x, const Layout& lx, const double* b, d
   const int nb = elem_blocks(n);
   hipLaunchKernelGGL(resid_dd_kernel, dim3(nb), dim3(kNT), 0, st, x, lx.pitch, lx.zpitch, b, r, lr.pitch, lr.zpitch,
                      n[0], n[1], n[2], taps, s, flag, partials);
-  return hipGetLastError();
+  return finish(FIN_RESID, s, partials, nb, 0.0, flag, 0, st);
 }
 
 hipError_t launch_pc_init(int dtype, void* S, double* lam, int64_t m, double h, hipStream_t st) {
@@ -385,7 +432,7 @@ hipError_t launch_pc_dot(int dtype, const void* r, const void* z, const Layout& 
   else
     hipLaunchKernelGGL(pc_dot_kernel<float>, dim3(nb), dim3(kNT), 0, st, (const float*)r, (const float*)z,
                        lay.pitch, lay.zpitch, n[0], n[1], n[2], s, start, partials);
-  return hipGetLastError();
+  return finish(FIN_PCDOT, s, partials, nb, 0.0, start, 1, st);
 }
 
 hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
@@ -401,7 +448,7 @@ hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const vo
                        (const float*)p, (const float*)q, lay.pitch, lay.zpitch, n[0], n[1], n[2], s,
                        partials);
   }
-  return hipGetLastError();
+  return finish(FIN_UPDATE, s, partials, nb, 0.0, 0, 1, st);
 }
 
 hipError_t launch_ir_prepare(const double* r64, const Layout& l64, float* r32, float* d32,
@@ -411,7 +458,7 @@ hipError_t launch_ir_prepare(const double* r64, const Layout& l64, float* r32, f
   hipLaunchKernelGGL(ir_prepare_kernel, dim3(nb), dim3(kNT), 0, st, r64, l64.pitch, l64.zpitch, r32,
                      d32, l32.pitch, l32.zpitch, n[0], n[1], n[2], s64, s32, inner_tol2, keep_direction,
                      partials);
-  return hipGetLastError();
+  return finish(FIN_IR, s32, partials, nb, inner_tol2, keep_direction, 0, st, s64);
 }
 
 hipError_t launch_ir_update(double* x64, const Layout& l64, const float* d32, const Layout& l32,
@@ -456,7 +503,7 @@ hipError_t launch_copy_norm(const double* src, int64_t sp, int64_t sz, double* d
   const int nb = elem_blocks(n);
   hipLaunchKernelGGL(copy_norm_kernel, dim3(nb), dim3(kNT), 0, st, src, sp, sz, dst, dp, dz, n[0], n[1], n[2], s,
                      tol2, partials);
-  return hipGetLastError();
+  return finish(FIN_RHS, s, partials, nb, tol2, 0, 0, st);
 }
 
 hipError_t launch_combine(const CombineTerms& t, const double* base, double* out, const Layout& lay,

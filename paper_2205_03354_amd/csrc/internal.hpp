@@ -133,6 +133,10 @@ struct Layout {
 
 constexpr int kElemBlocks = 1024;  // blocks of the element-wise kernels
 
+// The one-block second half of a grid reduction (see FinKind): sums the
+// partials of the kernel launched just before on `st` and finalises.
+hipError_t launch_finish(int fk, const FinArgs& f, hipStream_t st);
+
 hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
                             const Layout& lay, const int64_t* n, DevScalars* s, double* partials,
                             hipStream_t st);

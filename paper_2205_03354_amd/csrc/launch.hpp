@@ -165,6 +165,28 @@ Taps<T, sym_num_classes(PAT, R)> make_sym_taps(const KStencil& ks) {
   return t;
 }
 
+// The finish kernel of a sweep that reduces a dot product (after the sweep's
+// own launch on the same stream).
+template <int KIND>
+hipError_t finish_sweep(const DevScalars* scal, const double* partials, int blocks, double c2, int flag,
+                        hipStream_t st) {
+  const hipError_t e = hipGetLastError();
+  if constexpr (!kind_has_dot(KIND)) {
+    return e;
+  } else {
+    if (e != hipSuccess) return e;
+    FinArgs f;
+    f.s = const_cast<DevScalars*>(scal);
+    f.partials = partials;
+    f.n = blocks;
+    f.c = c2;
+    f.flag = flag;
+    f.skip_if_done = KIND == K_CGDIR ? 1 : 0;
+    const int fk = KIND == K_CGDIR ? FIN_CGDIR : (KIND == K_RESID ? FIN_RESID : FIN_RHS);
+    return launch_finish(fk, f, st);
+  }
+}
+
 // Waves of kernel `kern` (64-thread blocks) the device holds at once.
 template <typename K>
 int64_t resident_waves(K kern) {
@@ -194,7 +216,7 @@ hipError_t run2d(const SweepLaunch& L, hipStream_t st) {
     const auto taps = make_taps<T, num_taps(PAT, R, 2)>(*L.ks);
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), 0, st, a, taps);
   }
-  return hipGetLastError();
+  return finish_sweep<KIND>(a.scal, a.partials, blocks, a.c2, a.flag, st);
 }
 
 template <typename T, int KIND, int PAT, int R, bool PER, int NT>
@@ -205,7 +227,7 @@ hipError_t run3d(const SweepLaunch& L, hipStream_t st) {
   const auto taps = make_taps<T, num_taps(PAT, R, 3)>(*L.ks);
   hipLaunchKernelGGL((sweep3d_kernel<T, KIND, PAT, R, PER, NT>), dim3(blocks), dim3(NT), 0, st, a,
                      taps);
-  return hipGetLastError();
+  return finish_sweep<KIND>(a.scal, a.partials, blocks, a.c2, a.flag, st);
 }
 
 template <typename T, int KIND, int PAT, int R, bool PER>
@@ -219,7 +241,7 @@ hipError_t run3s(const SweepLaunch& L, hipStream_t st) {
   geom3s<T, TY>(L, R, a, &blocks, capacity);
   const auto taps = make_sym3_taps<T, PAT, R>(*L.ks);
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(64), 0, st, a, taps);
-  return hipGetLastError();
+  return finish_sweep<KIND>(a.scal, a.partials, blocks, a.c2, a.flag, st);
 }
 
 }  // namespace sc

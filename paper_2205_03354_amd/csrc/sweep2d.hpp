@@ -81,29 +81,6 @@ __device__ __forceinline__ int64_t wrap_once(int64_t a, int64_t n) {
   return a < 0 ? a + n : (a >= n ? a - n : a);
 }
 
-// Finalisers run by the last block of a reduction (thread 0).
-template <int KIND>
-__device__ __forceinline__ void finalize(DevScalars* s, double total, double tol2, int flag) {
-  if constexpr (KIND == K_CGDIR) {
-    s->pq = total;
-    if (!(total > 0.0) || !__builtin_isfinite(total)) {
-      s->done = 2;
-    } else {
-      s->alpha = (flag ? s->rz : s->rr) / total;  // flag: preconditioned, alpha = <r, z> / <p, A p>
-    }
-  } else if constexpr (KIND == K_RESID) {
-    s->rr_true = total;
-    if (flag) {
-      s->rr = total;
-      s->beta = 0.0;
-      s->done = (total <= s->rr_stop) ? 1 : 0;
-    }
-  } else if constexpr (KIND == K_BVPRHS || KIND == K_CHRHS) {
-    s->bb = total;
-    s->rr_stop = tol2 * total;
-  }
-}
-
 // ---------------------------------------------------------------- weights
 // Symmetric stencils carry one weight per class (d, a) = (|dx|, |dy|)
 // admitted by the pattern, ordered a-major then d.
@@ -495,13 +472,7 @@ __global__ void __launch_bounds__(64)
   else
     body(std::integral_constant<bool, false>{});
 
-  if constexpr (HAS_DOT) {
-    DevScalars* sc = a.scal;
-    const double c2 = a.c2;
-    const int flag = a.flag;
-    grid_reduce<64>(dot, tile, (int)gridDim.x, a.partials, &sc->ticket,
-                    [&](double total) { finalize<KIND>(sc, total, c2, flag); });
-  }
+  if constexpr (HAS_DOT) block_partial<64>(dot, tile, a.partials);
 }
 
 }  // namespace sc

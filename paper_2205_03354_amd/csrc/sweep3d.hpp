@@ -236,13 +236,7 @@ __global__ void __launch_bounds__(NT)
     });
   }
 
-  if constexpr (HAS_DOT) {
-    DevScalars* sc = a.scal;
-    const double c2 = a.c2;
-    const int flag = a.flag;
-    grid_reduce<NT>(dot, tile, (int)gridDim.x, a.partials, &sc->ticket,
-                    [&](double total) { finalize<KIND>(sc, total, c2, flag); });
-  }
+  if constexpr (HAS_DOT) block_partial<NT>(dot, tile, a.partials);
 }
 
 }  // namespace sc

@@ -418,13 +418,7 @@ __global__ void __launch_bounds__(64)
   else
     body(std::integral_constant<bool, false>{});
 
-  if constexpr (HAS_DOT) {
-    DevScalars* sc = a.scal;
-    const double c2 = a.c2;
-    const int flag = a.flag;
-    grid_reduce<64>(dot, tile, (int)gridDim.x, a.partials, &sc->ticket,
-                    [&](double total) { finalize<KIND>(sc, total, c2, flag); });
-  }
+  if constexpr (HAS_DOT) block_partial<64>(dot, tile, a.partials);
 }
 
 }  // namespace sc
