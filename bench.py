@@ -137,8 +137,30 @@ def solver_bench(native, torch, reps: int):
                      "p50_ms": round(1e3 * statistics.median(lat), 3),
                      "p99_ms": round(1e3 * lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)], 3),
                      "iterations": its, "rel_residual": rel}
+    # on-chip solver: one workgroup per problem; one problem, then batches
+    # of independent copies (each with its own u) solved concurrently
+    for name, count in (("f64_onchip", 1), ("f64_onchip_batch256", 256), ("f64_onchip_batch1024", 1024)):
+        lat = []
+        us = [torch.zeros_like(f) for _ in range(count)]
+        for i in range(reps + 1):
+            for u in us:
+                u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, sts = native.solve_biharmonic_batch(op, [(bvp.h, f, u, g, 2) for u in us], tol=1e-10)
+            t1 = time.perf_counter()
+            if i > 0:
+                lat.append(t1 - t0)
+        lat.sort()
+        out[name] = {"solves_per_s": round(count * len(lat) / sum(lat), 2),
+                     "batch": count,
+                     "p50_ms": round(1e3 * statistics.median(lat), 3),
+                     "p99_ms": round(1e3 * lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)], 3),
+                     "iterations": sts[0].iterations, "rel_residual": max(s.rel_residual for s in sts)}
     return {"workload": "2D biharmonic BVP, 65^2 nodes (63^2 unknowns), 13-point L o L, to 1e-10; plain CG "
-                        "and fast-Poisson preconditioned CG (_pcg)", **out}
+                        "and fast-Poisson preconditioned CG (_pcg) through the grid solver; plain CG on chip "
+                        "(one workgroup per problem), alone and in batches of independent problems; latency is "
+                        "per call (a batch completes together)", **out}
 
 
 def ch_bench(native, torch, steps: int):

@@ -266,6 +266,30 @@ sc_status sc_solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, 
                               const sc_solve_opts* opts, sc_grid* u, sc_solve_stats* stats,
                               sc_stream_t stream);
 
+/*
+ * A batch of small 2D biharmonic BVPs, each the problem of
+ * sc_solve_biharmonic (Sec. 3.3: plain CG in FP64 from the initial guess in
+ * u[i] on A0 x = f - A g_ring, stopped on the recurrence residual and
+ * confirmed on the true residual), solved concurrently with one workgroup
+ * per problem and all of its vectors on chip: the form for latency-bound
+ * sizes. One operator `op` (2D) for all problems; per problem i the spacing
+ * h[i], the FP64 grids f[i], u[i] and optionally g[i] (g NULL, or
+ * g[i].data NULL, for a zero ring; else halo >= radius), of one shape per
+ * problem with n0 n1 <= 4096 and (n0 + 2R)(n1 + 2R) <= 7936 (R the
+ * operator's pattern radius; 64 x 64 unknowns for the 13-point L o L).
+ * From opts: tol and max_iter; precision must be SC_PREC_F64 and precond
+ * SC_PC_NONE; check_every and use_graph do not apply. A problem's result
+ * does not depend on the rest of the batch. stats (count entries, may be
+ * NULL) receive every problem's statistics, `seconds` being the whole
+ * call's. Blocking. Returns SC_OK when every problem converged, else the
+ * status of the first problem that did not (SC_ENOTCONV, SC_EBREAKDOWN).
+ * Errors: SC_EINVAL, SC_EUNSUPPORTED (sizes, dimension, options),
+ * SC_ENOMEM, SC_EDEVICE.
+ */
+sc_status sc_solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t count, const sc_grid* f,
+                                    const sc_grid* g, const sc_solve_opts* opts, sc_grid* u,
+                                    sc_solve_stats* stats, sc_stream_t stream);
+
 /* Cahn-Hilliard step parameters (normalised form u_t = Lap(u^3 - u - eps^2 Lap u)). */
 typedef struct sc_ch_params {
   double h;    /* grid spacing (periodic unit domain: h = 1/n) */

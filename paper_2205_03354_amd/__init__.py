@@ -33,6 +33,7 @@ from ._native import (  # noqa: F401
     grid_diagnostics,
     grid_of,
     solve_biharmonic,
+    solve_biharmonic_batch,
     spinodal_energy,
     spinodal_params,
     spinodal_steps,

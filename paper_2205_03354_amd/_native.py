@@ -32,6 +32,7 @@ EXPORTED = (
     "sc_solve_biharmonic", "sc_ch_step", "sc_grid_diagnostics", "sc_status_str",
     "sc_last_error", "sc_version", "sc_server_create", "sc_server_submit", "sc_server_poll",
     "sc_server_cancel", "sc_server_load", "sc_server_destroy", "sc_spinodal_steps", "sc_spinodal_energy",
+    "sc_solve_biharmonic_batch",
     "sc_csr_assemble", "sc_csr_info",
     "sc_csr_spmv", "sc_csr_export", "sc_csr_free",
 )
@@ -128,6 +129,10 @@ def _load() -> ctypes.CDLL:
     L.sc_server_destroy.restype = None
     for name in ("sc_server_create", "sc_server_submit", "sc_server_poll", "sc_server_cancel", "sc_server_load"):
         getattr(L, name).restype = ctypes.c_int
+    L.sc_solve_biharmonic_batch.argtypes = [P, P, I32, ctypes.POINTER(SCGrid), ctypes.POINTER(SCGrid),
+                                            ctypes.POINTER(SCSolveOpts), ctypes.POINTER(SCGrid),
+                                            ctypes.POINTER(SCSolveStats), P]
+    L.sc_solve_biharmonic_batch.restype = ctypes.c_int
     L.sc_spinodal_steps.argtypes = [P, ctypes.POINTER(SCSpinodalParams), I32, ctypes.POINTER(SCSolveOpts),
                                     ctypes.POINTER(SCGrid), ctypes.POINTER(SCSpinodalStats), P]
     L.sc_spinodal_energy.argtypes = [ctypes.POINTER(SCGrid), ctypes.POINTER(SCSpinodalParams), P, P, P]
@@ -404,6 +409,27 @@ def solve_biharmonic(op: Stencil, h: float, f, u, g=None, g_halo: int = 0, tol: 
     if raise_on_error:
         _check(status)
     return _stats(st, status)
+
+
+def solve_biharmonic_batch(op: Stencil, problems, tol: float = 1e-10, max_iter: int = 10**6,
+                           raise_on_error: bool = True, stream=None):
+    """Solve a batch of small 2D BVPs, one workgroup each (sc_solve_biharmonic_batch).
+    problems: sequence of (h, f, u, g, g_halo) with g None for a zero ring.
+    Returns (status, [SolveStats per problem])."""
+    n = len(problems)
+    hs = (ctypes.c_double * max(n, 1))(*[float(p[0]) for p in problems])
+    fs = (SCGrid * max(n, 1))(*[grid_of(p[1], 0) for p in problems])
+    us = (SCGrid * max(n, 1))(*[grid_of(p[2], 0) for p in problems])
+    gs = (SCGrid * max(n, 1))()
+    for i, p in enumerate(problems):
+        if p[3] is not None:
+            gs[i] = grid_of(p[3], p[4])
+    o = _opts(tol, max_iter, SC_PREC_F64, 0.0, 64, True, SC_PC_NONE)
+    st = (SCSolveStats * max(n, 1))()
+    status = lib.sc_solve_biharmonic_batch(op.handle, hs, n, fs, gs, ctypes.byref(o), us, st, _stream(stream))
+    if raise_on_error:
+        _check(status)
+    return status, [_stats(st[i], status) for i in range(n)]
 
 
 def ch_step(lap: Stencil, u, h: float, eps: float, dt: float, S: float, tol: float = 1e-10,

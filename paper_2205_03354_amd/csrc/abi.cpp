@@ -155,6 +155,13 @@ sc_status sc_solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, 
   SC_GUARD(return sc::solve_biharmonic(op, h, f, g, opts, u, stats, reinterpret_cast<hipStream_t>(stream));)
 }
 
+sc_status sc_solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t count, const sc_grid* f,
+                                    const sc_grid* g, const sc_solve_opts* opts, sc_grid* u,
+                                    sc_solve_stats* stats, sc_stream_t stream) {
+  SC_GUARD(return sc::solve_biharmonic_batch(op, h, count, f, g, opts, u, stats,
+                                             reinterpret_cast<hipStream_t>(stream));)
+}
+
 sc_status sc_ch_step(const sc_stencil* lap, const sc_ch_params* prm, const sc_solve_opts* opts, sc_grid* u,
                      sc_solve_stats* stats, sc_stream_t stream) {
   SC_GUARD(return sc::ch_step(lap, prm, opts, u, stats, reinterpret_cast<hipStream_t>(stream));)

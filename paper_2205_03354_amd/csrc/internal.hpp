@@ -234,6 +234,11 @@ void* pool_alloc(size_t bytes);
 void pool_free(void* p);
 size_t esize(int dtype);
 
+// Batched small 2D BVPs, one workgroup per problem (small.hip).
+sc_status solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t count, const sc_grid* f,
+                                 const sc_grid* g, const sc_solve_opts* opts, sc_grid* u, sc_solve_stats* stats,
+                                 hipStream_t st);
+
 // IMEX steps of the spinodal-decomposition benchmark (imex.cpp).
 sc_status spinodal_steps(const sc_stencil* lap, const sc_spinodal_params* p, int32_t nsteps,
                          const sc_solve_opts* opts, sc_grid* c, sc_spinodal_stats* stats, hipStream_t st);

@@ -1,0 +1,398 @@
+// Batched biharmonic BVPs on small 2D grids (Sec. 3.3), one workgroup per
+// problem with every vector on chip.
+//
+// A grid of up to 4096 unknowns (and 7936 with its ring) fits one workgroup
+// of 512 threads holding up to eight points each in registers (x, r, p, b);
+// the search direction is
+// shared through an LDS tile that carries a zero ring of the stencil's
+// radius, so each iteration is one stencil pass over LDS and two workgroup
+// reductions, with no kernel launches or host round trips. The solve is the
+// same textbook CG as the large-grid path: x0 from u, b = f - A g_ring,
+// stop on the recurrence residual, confirm on the true residual b - A x
+// (restarting from it if the check fails), all in FP64. Reductions run in a
+// fixed order, so a problem's result does not depend on the rest of the
+// batch.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace sc {
+
+namespace {
+
+constexpr int kNT = 512;
+constexpr int kWaves = kNT / 64;
+constexpr int kMaxPts = 4096;      // unknowns per problem (eight per thread)
+constexpr int kMaxTile = 7936;     // LDS tile (unknowns plus ring), doubles: 62 KB
+constexpr int kSmallTaps = 64;
+constexpr int kMaxRestarts = 64;   // true-residual restarts before giving up
+
+struct SmallDesc {
+  const double* f;  // interiors
+  const double* g;  // NULL: zero ring
+  double* u;
+  int64_t pf, pg, pu;
+  int n0, n1;
+  double w[kSmallTaps];
+};
+
+struct SmallTaps {
+  int n;
+  int R;
+  int dx[kSmallTaps];
+  int dy[kSmallTaps];
+};
+
+struct SmallResult {
+  long long iter;
+  double rr_true;
+  double bb;
+  int status;
+  int outer;
+};
+
+// Sum of a and b over the workgroup, in a fixed order, returned to every
+// thread (two barriers).
+__device__ __forceinline__ void wg_sum2(double& a, double& b, double (*red)[2]) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wave][0] = a;
+    red[wave][1] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    sa += red[w][0];
+    sb += red[w][1];
+  }
+  __syncthreads();
+  a = sa;
+  b = sb;
+}
+
+template <int PPT>
+__global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restrict__ descs, SmallTaps taps,
+                                                       double tol2, long long max_iter,
+                                                       SmallResult* __restrict__ results) {
+  __shared__ double tile[kMaxTile];
+  __shared__ double red[kWaves][2];
+  __shared__ double sw[kSmallTaps];
+  __shared__ int soff[kSmallTaps];
+  const SmallDesc& d = descs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int R = taps.R;
+  const int n0 = d.n0, n1 = d.n1;
+  const int W = n0 + 2 * R;
+  const int H = n1 + 2 * R;
+  const int npts = n0 * n1;
+  const int nt = taps.n;
+  if (tid < nt) {
+    sw[tid] = d.w[tid];
+    soff[tid] = taps.dy[tid] * W + taps.dx[tid];
+  }
+  // the ring values of g (zero inside) for b = f - A g_ring
+  for (int i = tid; i < W * H; i += kNT) {
+    const int ty = i / W - R, tx = i % W - R;
+    const bool ring = tx < 0 || tx >= n0 || ty < 0 || ty >= n1;
+    tile[i] = (ring && d.g) ? d.g[(int64_t)ty * d.pg + tx] : 0.0;
+  }
+  __syncthreads();
+
+  int base[PPT];
+  bool valid[PPT];
+  double x[PPT], r[PPT], p[PPT], b[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int k = tid + j * kNT;
+    valid[j] = k < npts;
+    const int ix = valid[j] ? k % n0 : 0, iy = valid[j] ? k / n0 : 0;
+    base[j] = (iy + R) * W + ix + R;
+    double ag = 0.0;
+#pragma unroll 1
+    for (int t = 0; t < nt; ++t) ag = __builtin_fma(sw[t], tile[base[j] + soff[t]], ag);
+    b[j] = valid[j] ? d.f[(int64_t)iy * d.pf + ix] - ag : 0.0;
+    x[j] = valid[j] ? d.u[(int64_t)iy * d.pu + ix] : 0.0;
+  }
+  __syncthreads();
+  // the Krylov vectors see a zero ring
+  for (int i = tid; i < W * H; i += kNT) tile[i] = 0.0;
+  __syncthreads();
+
+  // q = A v at this thread's points, v given in registers (taps outer,
+  // points inner: one accumulator per point)
+  auto apply = [&](const double (&v)[PPT], double (&q)[PPT]) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+      if (valid[j]) tile[base[j]] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) q[j] = 0.0;
+#pragma unroll 1
+    for (int t = 0; t < nt; ++t) {
+      const double wt = sw[t];
+      const int o = soff[t];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) q[j] = __builtin_fma(wt, tile[base[j] + o], q[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+      if (!valid[j]) q[j] = 0.0;
+    __syncthreads();
+  };
+
+  double q[PPT];
+  // true residual r = b - A x, <r, r>, <b, b>
+  apply(x, q);
+  double rr = 0.0, bb = 0.0;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    r[j] = b[j] - q[j];
+    p[j] = r[j];
+    rr += r[j] * r[j];
+    bb += b[j] * b[j];
+  }
+  wg_sum2(rr, bb, red);
+  const double rr_stop = tol2 * bb;
+  double rr_true = rr;
+  long long it = 0;
+  int outer = 1, status = SC_OK;
+  bool converged = rr_true <= rr_stop;
+  while (!converged) {
+    if (it >= max_iter) {
+      status = SC_ENOTCONV;
+      break;
+    }
+    apply(p, q);
+    double pq = 0.0, unused = 0.0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) pq += p[j] * q[j];
+    wg_sum2(pq, unused, red);
+    if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
+      status = SC_EBREAKDOWN;
+      break;
+    }
+    const double alpha = rr / pq;
+    double rn = 0.0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      x[j] = __builtin_fma(alpha, p[j], x[j]);
+      r[j] = __builtin_fma(-alpha, q[j], r[j]);
+      rn += r[j] * r[j];
+    }
+    wg_sum2(rn, unused, red);
+    ++it;
+    if (rn <= rr_stop) {
+      // confirm on the true residual; restart the recurrence from it if not
+      apply(x, q);
+      double rt = 0.0;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        r[j] = b[j] - q[j];
+        p[j] = r[j];
+        rt += r[j] * r[j];
+      }
+      wg_sum2(rt, unused, red);
+      rr_true = rt;
+      ++outer;
+      if (rt <= rr_stop) {
+        converged = true;
+      } else if (outer > kMaxRestarts) {
+        status = SC_ENOTCONV;
+        break;
+      }
+      rr = rt;
+      continue;
+    }
+    const double beta = rn / rr;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) p[j] = __builtin_fma(beta, p[j], r[j]);
+    rr = rn;
+  }
+  if (status != SC_OK) {
+    // the true residual of the returned iterate
+    apply(x, q);
+    double rt = 0.0, unused = 0.0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const double e = b[j] - q[j];
+      rt += e * e;
+    }
+    wg_sum2(rt, unused, red);
+    rr_true = rt;
+  }
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    if (!valid[j]) continue;
+    const int k = tid + j * kNT;
+    d.u[(int64_t)(k / n0) * d.pu + k % n0] = x[j];
+  }
+  if (tid == 0) {
+    SmallResult& o = results[blockIdx.x];
+    o.iter = it;
+    o.rr_true = rr_true;
+    o.bb = bb;
+    o.status = status;
+    o.outer = outer;
+  }
+}
+
+}  // namespace
+
+sc_status solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t count, const sc_grid* f,
+                                 const sc_grid* g, const sc_solve_opts* opts, sc_grid* u, sc_solve_stats* stats,
+                                 hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  sc_status r;
+  if (!op || !h || !f || !u || count < 0) {
+    set_error("NULL operator, spacing or grid arrays, or a negative count");
+    return SC_EINVAL;
+  }
+  if (op->dim != 2) {
+    set_error("the batched solver takes 2D operators");
+    return SC_EUNSUPPORTED;
+  }
+  if (count == 0) return SC_OK;
+  sc_solve_opts o;
+  fill_opts(opts, &o);
+  if ((r = check_opts(o)) != SC_OK) return r;
+  if (o.precision != SC_PREC_F64 || o.precond != SC_PC_NONE) {
+    set_error("the batched solver runs plain CG in FP64");
+    return SC_EUNSUPPORTED;
+  }
+  std::vector<SmallDesc> descs((size_t)count);
+  SmallTaps taps{};
+  for (int i = 0; i < count; ++i) {
+    const sc_grid* gi = g ? &g[i] : nullptr;
+    if (gi && !gi->data) gi = nullptr;
+    if ((r = check_grid(&f[i], "f")) != SC_OK || (r = check_grid(&u[i], "u")) != SC_OK) return r;
+    if (gi && (r = check_grid(gi, "g")) != SC_OK) return r;
+    const bool same = f[i].dim == 2 && u[i].dim == 2 && f[i].n[0] == u[i].n[0] && f[i].n[1] == u[i].n[1] &&
+                      (!gi || (gi->dim == 2 && gi->n[0] == u[i].n[0] && gi->n[1] == u[i].n[1]));
+    if (!same || f[i].dtype != SC_F64 || u[i].dtype != SC_F64 || (gi && gi->dtype != SC_F64)) {
+      set_error("problem %d: f, g and u must be 2D FP64 grids of one shape", i);
+      return SC_EINVAL;
+    }
+    KStencil ks;
+    if ((r = make_kstencil(op, h[i], &ks)) != SC_OK) return r;
+    const TapTable tt = tap_table(ks);
+    if (tt.n > kSmallTaps) {
+      set_error("the batched solver takes at most %d taps", kSmallTaps);
+      return SC_EUNSUPPORTED;
+    }
+    if (i == 0) {
+      taps.n = tt.n;
+      taps.R = ks.R;
+      for (int t = 0; t < tt.n; ++t) {
+        taps.dx[t] = tt.off[t][0];
+        taps.dy[t] = tt.off[t][1];
+      }
+    } else {
+      bool ok = tt.n == taps.n && ks.R == taps.R;
+      for (int t = 0; ok && t < tt.n; ++t) ok = taps.dx[t] == tt.off[t][0] && taps.dy[t] == tt.off[t][1];
+      if (!ok) {
+        set_error("problem %d: the operator's taps changed with h", i);
+        return SC_EINVAL;
+      }
+    }
+    const int64_t n0 = u[i].n[0], n1 = u[i].n[1];
+    const int R = ks.R;
+    if (n0 * n1 > kMaxPts || (n0 + 2 * R) * (n1 + 2 * R) > kMaxTile) {
+      set_error("problem %d: %lld x %lld unknowns exceed the on-chip limit (%d unknowns, %d with the ring)", i,
+                (long long)n0, (long long)n1, kMaxPts, kMaxTile);
+      return SC_EUNSUPPORTED;
+    }
+    if (gi && gi->halo < R) {
+      set_error("problem %d: g must carry a ring of width >= radius (%d < %d)", i, gi->halo, R);
+      return SC_EINVAL;
+    }
+    SmallDesc& dd = descs[(size_t)i];
+    dd.f = static_cast<const double*>(interior(&f[i]));
+    dd.g = gi ? static_cast<const double*>(interior(gi)) : nullptr;
+    dd.u = static_cast<double*>(interior(&u[i]));
+    dd.pf = f[i].pitch[0];
+    dd.pg = gi ? gi->pitch[0] : 0;
+    dd.pu = u[i].pitch[0];
+    dd.n0 = (int)n0;
+    dd.n1 = (int)n1;
+    for (int t = 0; t < tt.n; ++t) dd.w[t] = tt.w[t];
+  }
+  // One launch per register class (points per thread), so that a problem
+  // always runs in the instantiation its own size selects and its result
+  // cannot depend on the rest of the batch.
+  auto cls = [](const SmallDesc& q) {
+    const int pts = q.n0 * q.n1;
+    return pts <= kNT ? 0 : pts <= 2 * kNT ? 1 : pts <= 4 * kNT ? 2 : 3;
+  };
+  std::vector<int> order;
+  int first[5] = {0, 0, 0, 0, 0};
+  for (int c = 0; c < 4; ++c) {
+    first[c] = (int)order.size();
+    for (int i = 0; i < count; ++i)
+      if (cls(descs[(size_t)i]) == c) order.push_back(i);
+  }
+  first[4] = count;
+  std::vector<SmallDesc> sorted((size_t)count);
+  for (int k = 0; k < count; ++k) sorted[(size_t)k] = descs[(size_t)order[(size_t)k]];
+  void* ddev = pool_alloc(sorted.size() * sizeof(SmallDesc));
+  void* rdev = pool_alloc((size_t)count * sizeof(SmallResult));
+  struct Release {
+    hipStream_t st;
+    void* a;
+    void* b;
+    ~Release() {
+      (void)hipStreamSynchronize(st);
+      pool_free(a);
+      pool_free(b);
+    }
+  } rel{st, ddev, rdev};
+  if (!ddev || !rdev) {
+    set_error("device allocation failed");
+    return SC_ENOMEM;
+  }
+  SC_HIP_CHECK(hipMemcpyAsync(ddev, sorted.data(), sorted.size() * sizeof(SmallDesc), hipMemcpyHostToDevice, st));
+  const double tol2 = o.tol * o.tol;
+  const auto* dp = static_cast<const SmallDesc*>(ddev);
+  auto* rp = static_cast<SmallResult*>(rdev);
+  const long long mi = (long long)o.max_iter;
+  for (int c = 0; c < 4; ++c) {
+    const int k0 = first[c], nk = first[c + 1] - first[c];
+    if (nk == 0) continue;
+    const dim3 grid((unsigned)nk), block(kNT);
+    if (c == 0) hipLaunchKernelGGL(small_cg_kernel<1>, grid, block, 0, st, dp + k0, taps, tol2, mi, rp + k0);
+    if (c == 1) hipLaunchKernelGGL(small_cg_kernel<2>, grid, block, 0, st, dp + k0, taps, tol2, mi, rp + k0);
+    if (c == 2) hipLaunchKernelGGL(small_cg_kernel<4>, grid, block, 0, st, dp + k0, taps, tol2, mi, rp + k0);
+    if (c == 3) hipLaunchKernelGGL(small_cg_kernel<8>, grid, block, 0, st, dp + k0, taps, tol2, mi, rp + k0);
+    SC_HIP_CHECK(hipGetLastError());
+  }
+  std::vector<SmallResult> sres((size_t)count), res((size_t)count);
+  SC_HIP_CHECK(hipMemcpyAsync(sres.data(), rdev, sres.size() * sizeof(SmallResult), hipMemcpyDeviceToHost, st));
+  SC_HIP_CHECK(hipStreamSynchronize(st));
+  for (int k = 0; k < count; ++k) res[(size_t)order[(size_t)k]] = sres[(size_t)k];
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  sc_status worst = SC_OK;
+  for (int i = 0; i < count; ++i) {
+    const SmallResult& q = res[(size_t)i];
+    if (stats) {
+      stats[i].iterations = q.iter;
+      stats[i].outer = q.outer;
+      stats[i].bnorm = std::sqrt(q.bb);
+      stats[i].rel_residual = q.bb > 0 ? std::sqrt(q.rr_true / q.bb) : 0.0;
+      stats[i].seconds = secs;
+    }
+    if (q.status != SC_OK && worst == SC_OK) worst = (sc_status)q.status;
+  }
+  if (worst != SC_OK) set_error("at least one problem of the batch did not converge (see its statistics)");
+  return worst;
+}
+
+}  // namespace sc
