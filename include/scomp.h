@@ -225,6 +225,9 @@ typedef struct sc_solve_opts {
   int32_t use_graph;    /* 1: replay each block of check_every iterations from a
                            captured hipGraph; 0: plain launches */
   int32_t precond;      /* sc_precond (biharmonic BVP only; ignored for CH) */
+  int32_t onchip;       /* 1: a 2D FP64 unpreconditioned BVP that fits one
+                           workgroup (see sc_solve_biharmonic_batch) is solved on
+                           chip by one kernel; 0: always the grid solver */
 } sc_solve_opts;
 
 typedef struct sc_solve_stats {
@@ -237,7 +240,7 @@ typedef struct sc_solve_stats {
 
 /* Fill opts with defaults: tol 1e-10, max_iter 10^7, SC_PREC_F64,
  * inner_tol 0 (the precision's default), check_every 64, use_graph 1,
- * precond SC_PC_NONE. */
+ * precond SC_PC_NONE, onchip 1. */
 void sc_solve_opts_default(sc_solve_opts* opts);
 
 /*

@@ -52,7 +52,7 @@ class SCGrid(ctypes.Structure):
 class SCSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("precond", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("onchip", ctypes.c_int32)]
 
 
 class SCSolveStats(ctypes.Structure):
@@ -378,7 +378,8 @@ class SolveStats:
     status: int
 
 
-def _opts(tol, max_iter, precision, inner_tol, check_every, use_graph=True, precond=SC_PC_NONE) -> SCSolveOpts:
+def _opts(tol, max_iter, precision, inner_tol, check_every, use_graph=True, precond=SC_PC_NONE,
+          onchip=True) -> SCSolveOpts:
     o = SCSolveOpts()
     lib.sc_solve_opts_default(ctypes.byref(o))
     o.tol = tol
@@ -388,6 +389,7 @@ def _opts(tol, max_iter, precision, inner_tol, check_every, use_graph=True, prec
     o.check_every = int(check_every)
     o.use_graph = 1 if use_graph else 0
     o.precond = int(precond)
+    o.onchip = 1 if onchip else 0
     return o
 
 
@@ -398,11 +400,11 @@ def _stats(s: SCSolveStats, status: int) -> SolveStats:
 def solve_biharmonic(op: Stencil, h: float, f, u, g=None, g_halo: int = 0, tol: float = 1e-10,
                      max_iter: int = 10**7, precision: int = SC_PREC_F64, inner_tol: float = 0.0,
                      check_every: int = 64, use_graph: bool = True, precond: int = SC_PC_NONE,
-                     raise_on_error: bool = True, stream=None) -> SolveStats:
+                     onchip: bool = True, raise_on_error: bool = True, stream=None) -> SolveStats:
     """A u = f at the unknowns with the ring prescribed by g (see scomp.h)."""
     gf, gu = grid_of(f, 0), grid_of(u, 0)
     gg = ctypes.byref(grid_of(g, g_halo)) if g is not None else None
-    o = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph, precond)
+    o = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph, precond, onchip)
     st = SCSolveStats()
     status = lib.sc_solve_biharmonic(op.handle, float(h), ctypes.byref(gf), gg, ctypes.byref(o), ctypes.byref(gu),
                                      ctypes.byref(st), _stream(stream))
@@ -509,11 +511,11 @@ class Server:
     def __init__(self, hbm_budget: int = 0, max_slots: int = 16, tol: float = 1e-10,
                  precision: int = SC_PREC_F64, inner_tol: float = 0.0, check_every: int = 64,
                  use_graph: bool = True, max_iter: int = 10**7, fake_device: bool = False,
-                 precond: int = SC_PC_NONE):
+                 precond: int = SC_PC_NONE, onchip: bool = True):
         o = SCServerOpts()
         o.hbm_budget = int(hbm_budget)
         o.max_slots = int(max_slots)
-        o.solve = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph, precond)
+        o.solve = _opts(tol, max_iter, precision, inner_tol, check_every, use_graph, precond, onchip)
         o.fake_device = 1 if fake_device else 0
         h = ctypes.c_void_p()
         _check(lib.sc_server_create(ctypes.byref(o), ctypes.byref(h)))

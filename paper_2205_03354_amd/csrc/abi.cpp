@@ -147,6 +147,7 @@ void sc_solve_opts_default(sc_solve_opts* o) {
   o->check_every = 64;
   o->use_graph = 1;
   o->precond = SC_PC_NONE;
+  o->onchip = 1;
 }
 
 sc_status sc_solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, const sc_grid* g,

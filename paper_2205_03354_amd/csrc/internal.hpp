@@ -234,6 +234,38 @@ void* pool_alloc(size_t bytes);
 void pool_free(void* p);
 size_t esize(int dtype);
 
+// On-chip CG for small 2D BVPs, one workgroup per problem (small.hip).
+constexpr int kSmallTaps = 64;
+constexpr int kSmallMaxPoints = 4096;  // unknowns per problem
+constexpr int kSmallMaxTile = 7936;    // unknowns plus the ring of the pattern radius
+struct SmallDesc {
+  const double* f;  // interiors
+  const double* g;  // NULL: zero ring
+  double* u;        // initial guess in, solution out
+  int64_t pf, pg, pu;
+  int n0, n1;
+  double w[kSmallTaps];
+};
+struct SmallTaps {
+  int n;
+  int R;
+  int dx[kSmallTaps];
+  int dy[kSmallTaps];
+};
+struct SmallResult {
+  long long iter;
+  double rr_true;
+  double bb;
+  int status;
+  int outer;
+};
+// Register class (0..3) of an n0 x n1 problem of pattern radius R, or -1
+// when it does not fit one workgroup.
+int small_class(int64_t n0, int64_t n1, int R);
+// Solve `count` problems of one class (descs and results in device memory).
+hipError_t launch_small_cg(const SmallDesc* descs, const SmallTaps& taps, int count, int cls, double tol2,
+                           long long max_iter, SmallResult* results, hipStream_t st);
+
 // Batched small 2D BVPs, one workgroup per problem (small.hip).
 sc_status solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t count, const sc_grid* f,
                                  const sc_grid* g, const sc_solve_opts* opts, sc_grid* u, sc_solve_stats* stats,

@@ -28,35 +28,13 @@ constexpr int kNT = 512;
 constexpr int kWaves = kNT / 64;
 constexpr int kMaxPts = 4096;      // unknowns per problem (eight per thread)
 constexpr int kMaxTile = 7936;     // LDS tile (unknowns plus ring), doubles: 62 KB
-constexpr int kSmallTaps = 64;
+static_assert(kMaxPts == kSmallMaxPoints && kMaxTile == kSmallMaxTile, "limits");
 constexpr int kMaxRestarts = 64;   // true-residual restarts before giving up
 
-struct SmallDesc {
-  const double* f;  // interiors
-  const double* g;  // NULL: zero ring
-  double* u;
-  int64_t pf, pg, pu;
-  int n0, n1;
-  double w[kSmallTaps];
-};
-
-struct SmallTaps {
-  int n;
-  int R;
-  int dx[kSmallTaps];
-  int dy[kSmallTaps];
-};
-
-struct SmallResult {
-  long long iter;
-  double rr_true;
-  double bb;
-  int status;
-  int outer;
-};
-
 // Sum of a and b over the workgroup, in a fixed order, returned to every
-// thread (two barriers).
+// thread (one barrier). Consecutive calls must alternate between two `red`
+// buffers: a buffer is rewritten only after the barrier of the call in
+// between, which every thread reaches after reading it.
 __device__ __forceinline__ void wg_sum2(double& a, double& b, double (*red)[2]) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -75,7 +53,6 @@ __device__ __forceinline__ void wg_sum2(double& a, double& b, double (*red)[2]) 
     sa += red[w][0];
     sb += red[w][1];
   }
-  __syncthreads();
   a = sa;
   b = sb;
 }
@@ -85,7 +62,7 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
                                                        double tol2, long long max_iter,
                                                        SmallResult* __restrict__ results) {
   __shared__ double tile[kMaxTile];
-  __shared__ double red[kWaves][2];
+  __shared__ double red2[2][kWaves][2];
   __shared__ double sw[kSmallTaps];
   __shared__ int soff[kSmallTaps];
   const SmallDesc& d = descs[blockIdx.x];
@@ -128,8 +105,14 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
   for (int i = tid; i < W * H; i += kNT) tile[i] = 0.0;
   __syncthreads();
 
+  int rb = 0;  // the reduction buffer of the next wg_sum2
+  auto reduce2 = [&](double& a, double& b) {
+    wg_sum2(a, b, red2[rb]);
+    rb ^= 1;
+  };
   // q = A v at this thread's points, v given in registers (taps outer,
-  // points inner: one accumulator per point)
+  // points inner: one accumulator per point). Every call is followed by a
+  // reduction, whose barrier orders these tile reads before the next writes.
   auto apply = [&](const double (&v)[PPT], double (&q)[PPT]) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
@@ -147,7 +130,6 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
       if (!valid[j]) q[j] = 0.0;
-    __syncthreads();
   };
 
   double q[PPT];
@@ -161,7 +143,7 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
     rr += r[j] * r[j];
     bb += b[j] * b[j];
   }
-  wg_sum2(rr, bb, red);
+  reduce2(rr, bb);
   const double rr_stop = tol2 * bb;
   double rr_true = rr;
   long long it = 0;
@@ -176,7 +158,7 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
     double pq = 0.0, unused = 0.0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) pq += p[j] * q[j];
-    wg_sum2(pq, unused, red);
+    reduce2(pq, unused);
     if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
       status = SC_EBREAKDOWN;
       break;
@@ -189,7 +171,7 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
       r[j] = __builtin_fma(-alpha, q[j], r[j]);
       rn += r[j] * r[j];
     }
-    wg_sum2(rn, unused, red);
+    reduce2(rn, unused);
     ++it;
     if (rn <= rr_stop) {
       // confirm on the true residual; restart the recurrence from it if not
@@ -201,7 +183,7 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
         p[j] = r[j];
         rt += r[j] * r[j];
       }
-      wg_sum2(rt, unused, red);
+      reduce2(rt, unused);
       rr_true = rt;
       ++outer;
       if (rt <= rr_stop) {
@@ -227,7 +209,7 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
       const double e = b[j] - q[j];
       rt += e * e;
     }
-    wg_sum2(rt, unused, red);
+    reduce2(rt, unused);
     rr_true = rt;
   }
 #pragma unroll
@@ -247,6 +229,26 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
 }
 
 }  // namespace
+
+int small_class(int64_t n0, int64_t n1, int R) {
+  if (n0 < 1 || n1 < 1 || n0 * n1 > kMaxPts || (n0 + 2 * R) * (n1 + 2 * R) > kMaxTile) return -1;
+  const int64_t pts = n0 * n1;
+  return pts <= kNT ? 0 : pts <= 2 * kNT ? 1 : pts <= 4 * kNT ? 2 : 3;
+}
+
+hipError_t launch_small_cg(const SmallDesc* descs, const SmallTaps& taps, int count, int cls, double tol2,
+                           long long max_iter, SmallResult* results, hipStream_t st) {
+  if (count < 1) return hipSuccess;
+  const dim3 grid((unsigned)count), block(kNT);
+  switch (cls) {
+    case 0: hipLaunchKernelGGL(small_cg_kernel<1>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
+    case 1: hipLaunchKernelGGL(small_cg_kernel<2>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
+    case 2: hipLaunchKernelGGL(small_cg_kernel<4>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
+    case 3: hipLaunchKernelGGL(small_cg_kernel<8>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 sc_status solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t count, const sc_grid* f,
                                  const sc_grid* g, const sc_solve_opts* opts, sc_grid* u, sc_solve_stats* stats,
@@ -306,7 +308,7 @@ sc_status solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t 
     }
     const int64_t n0 = u[i].n[0], n1 = u[i].n[1];
     const int R = ks.R;
-    if (n0 * n1 > kMaxPts || (n0 + 2 * R) * (n1 + 2 * R) > kMaxTile) {
+    if (small_class(n0, n1, R) < 0) {
       set_error("problem %d: %lld x %lld unknowns exceed the on-chip limit (%d unknowns, %d with the ring)", i,
                 (long long)n0, (long long)n1, kMaxPts, kMaxTile);
       return SC_EUNSUPPORTED;
@@ -329,10 +331,7 @@ sc_status solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t 
   // One launch per register class (points per thread), so that a problem
   // always runs in the instantiation its own size selects and its result
   // cannot depend on the rest of the batch.
-  auto cls = [](const SmallDesc& q) {
-    const int pts = q.n0 * q.n1;
-    return pts <= kNT ? 0 : pts <= 2 * kNT ? 1 : pts <= 4 * kNT ? 2 : 3;
-  };
+  auto cls = [&](const SmallDesc& q) { return small_class(q.n0, q.n1, taps.R); };
   std::vector<int> order;
   int first[5] = {0, 0, 0, 0, 0};
   for (int c = 0; c < 4; ++c) {
@@ -367,12 +366,7 @@ sc_status solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t 
   for (int c = 0; c < 4; ++c) {
     const int k0 = first[c], nk = first[c + 1] - first[c];
     if (nk == 0) continue;
-    const dim3 grid((unsigned)nk), block(kNT);
-    if (c == 0) hipLaunchKernelGGL(small_cg_kernel<1>, grid, block, 0, st, dp + k0, taps, tol2, mi, rp + k0);
-    if (c == 1) hipLaunchKernelGGL(small_cg_kernel<2>, grid, block, 0, st, dp + k0, taps, tol2, mi, rp + k0);
-    if (c == 2) hipLaunchKernelGGL(small_cg_kernel<4>, grid, block, 0, st, dp + k0, taps, tol2, mi, rp + k0);
-    if (c == 3) hipLaunchKernelGGL(small_cg_kernel<8>, grid, block, 0, st, dp + k0, taps, tol2, mi, rp + k0);
-    SC_HIP_CHECK(hipGetLastError());
+    SC_HIP_CHECK(launch_small_cg(dp + k0, taps, nk, c, tol2, mi, rp + k0, st));
   }
   std::vector<SmallResult> sres((size_t)count), res((size_t)count);
   SC_HIP_CHECK(hipMemcpyAsync(sres.data(), rdev, sres.size() * sizeof(SmallResult), hipMemcpyDeviceToHost, st));

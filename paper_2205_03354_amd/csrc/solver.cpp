@@ -161,8 +161,16 @@ void pinned_pair_free(DevScalars* p) {
   g_pin_free.push_back(p);
 }
 
+bool task_onchip(const TaskSpec& sp) {
+  if (sp.kind != TASK_BVP || sp.dim != 2 || sp.o.precision != SC_PREC_F64 || sp.o.precond != SC_PC_NONE ||
+      !sp.o.onchip)
+    return false;
+  return tap_table(sp.ksA).n <= kSmallTaps && small_class(sp.n[0], sp.n[1], sp.ksA.R) >= 0;
+}
+
 size_t task_footprint(const TaskSpec& sp) {
   const int halo = sp.kind == TASK_BVP ? sp.ksA.R : 0;
+  if (task_onchip(sp)) return vec_bytes(sp.dim, sp.n, halo, SC_F64) + 4096;
   const bool f32 = sp.o.precision != SC_PREC_F64;
   size_t b = 0;
   const size_t v64 = vec_bytes(sp.dim, sp.n, halo, SC_F64);
@@ -224,6 +232,31 @@ sc_status SolveTask::init(const TaskSpec& spec, hipStream_t st) {
     return SC_ENOMEM;
   }
   h32_ = h64_ + 1;
+  onchip_ = task_onchip(spec);
+  if (onchip_) {
+    // x, the problem descriptor and the result; the kernel does the rest
+    static_assert(sizeof(SmallResult) <= sizeof(DevScalars), "result slot");
+    dev_block_ = pool_alloc(4096);
+    if (!dev_block_) {
+      set_error("device allocation failed");
+      return SC_ENOMEM;
+    }
+    allocs_.push_back(dev_block_);
+    bytes_ += 4096;
+    sdesc_dev_ = static_cast<SmallDesc*>(dev_block_);
+    sres_dev_ = reinterpret_cast<SmallResult*>(static_cast<char*>(dev_block_) + 2048);
+    staps_.n = taps_.n;
+    staps_.R = spec.ksA.R;
+    for (int t = 0; t < taps_.n; ++t) {
+      staps_.dx[t] = taps_.off[t][0];
+      staps_.dy[t] = taps_.off[t][1];
+      sdesc_.w[t] = taps_.w[t];
+    }
+    sc_status s;
+    if ((s = make(&x_, SC_F64)) != SC_OK) return s;
+    phase_ = P_NONE;
+    return SC_OK;
+  }
   const size_t slots = (size_t)partial_slots(spec_);
   const size_t blk = 2 * sizeof(DevScalars) + 256 + slots * 3 * sizeof(double);
   dev_block_ = pool_alloc(blk);
@@ -423,6 +456,25 @@ sc_status SolveTask::enqueue_block(bool f32) {
 
 sc_status SolveTask::start(const GridView& u0, const GridView& f, const GridView* g) {
   SC_HIP_CHECK(launch_copy(u0.p, u0.pitch, u0.zpitch, (double*)x_.base, x_.lay.pitch, x_.lay.zpitch, spec_.n, st_));
+  if (onchip_) {
+    sdesc_.f = f.p;
+    sdesc_.pf = f.pitch;
+    sdesc_.g = g ? g->p : nullptr;
+    sdesc_.pg = g ? g->pitch : 0;
+    sdesc_.u = static_cast<double*>(x_.base);
+    sdesc_.pu = x_.lay.pitch;
+    sdesc_.n0 = (int)spec_.n[0];
+    sdesc_.n1 = (int)spec_.n[1];
+    SC_HIP_CHECK(hipMemcpyAsync(sdesc_dev_, &sdesc_, sizeof(SmallDesc), hipMemcpyHostToDevice, st_));
+    SC_HIP_CHECK(launch_small_cg(sdesc_dev_, staps_, 1, small_class(spec_.n[0], spec_.n[1], spec_.ksA.R),
+                                 spec_.o.tol * spec_.o.tol, (long long)spec_.o.max_iter, sres_dev_, st_));
+    // the result lands in the (otherwise unused) FP32 host slot; iter < 0 until then
+    SmallResult* hr = reinterpret_cast<SmallResult*>(h32_);
+    __atomic_store_n(&hr->iter, -1LL, __ATOMIC_RELEASE);
+    SC_HIP_CHECK(hipMemcpyAsync(hr, sres_dev_, sizeof(SmallResult), hipMemcpyDeviceToHost, st_));
+    phase_ = P_ONCHIP;
+    return SC_OK;
+  }
   const double tol2 = spec_.o.tol * spec_.o.tol;
   sc_status s;
   if (spec_.kind == TASK_BVP) {
@@ -530,6 +582,22 @@ sc_status SolveTask::advance(bool* done) {
     return stalled_ >= 3;
   };
   switch (phase_) {
+    case P_ONCHIP: {
+      const SmallResult* hr = reinterpret_cast<const SmallResult*>(h32_);
+      if (__atomic_load_n(&hr->iter, __ATOMIC_ACQUIRE) < 0) return SC_OK;  // not landed yet
+      h64_->iter = hr->iter;
+      h64_->bb = hr->bb;
+      h64_->rr_true = hr->rr_true;
+      outer_ = hr->outer;
+      const sc_status st = (sc_status)hr->status;
+      if (st == SC_ENOTCONV)
+        set_error("CG did not reach the tolerance (relative residual %g after %lld iterations)",
+                  hr->bb > 0 ? std::sqrt(hr->rr_true / hr->bb) : 0.0, hr->iter);
+      else if (st == SC_EBREAKDOWN)
+        set_error("CG breakdown: <p, Ap> <= 0 after %lld iterations", hr->iter);
+      finish(st);
+      break;
+    }
     case P_CHECK64:
       if (h64_->rr_true <= h64_->rr_stop) {
         finish(SC_OK);

@@ -40,6 +40,9 @@ struct TaskSpec {
 
 // Device bytes a task of this shape holds while it is alive.
 size_t task_footprint(const TaskSpec& spec);
+// The task is a small 2D FP64 BVP without preconditioner that the options
+// allow on chip and that fits one workgroup.
+bool task_onchip(const TaskSpec& spec);
 
 // Fast-Poisson preconditioner z = L_D^-2 r (see precond.cpp).
 class FastPoisson {
@@ -91,7 +94,7 @@ class SolveTask {
   size_t footprint() const { return bytes_; }
 
  private:
-  enum Phase { P_NONE, P_CHECK64, P_ITER64, P_FINAL, P_OUTER, P_INNER, P_DONE };
+  enum Phase { P_NONE, P_CHECK64, P_ITER64, P_FINAL, P_OUTER, P_INNER, P_ONCHIP, P_DONE };
   struct Vec {
     void* alloc = nullptr;
     void* base = nullptr;
@@ -142,6 +145,11 @@ class SolveTask {
   bool fell_back_ = false;     // a mixed-precision solve that continued in FP64
   bool pc_ = false;            // preconditioned CG (BVP, fast-Poisson)
   TapTable taps_;              // the operator's taps (double-double residual)
+  bool onchip_ = false;        // one-kernel solve of a small 2D BVP (see small.hip)
+  SmallDesc sdesc_{};
+  SmallTaps staps_{};
+  SmallDesc* sdesc_dev_ = nullptr;
+  SmallResult* sres_dev_ = nullptr;
   FastPoisson pc64_, pc32_;
   Vec z64_, t64_, z32_, t32_;  // z = M^-1 r and its scratch, per precision
   sc_solve_stats stats_{};

@@ -128,3 +128,22 @@ def test_iteration_limit_and_errors(native):
         native.solve_biharmonic_batch(stencils.biharmonic(3), [(0.1, big, big.clone(), None, 0)])
     status, st = native.solve_biharmonic_batch(op, [])
     assert status == native.SC_OK and st == []
+
+
+def test_blocking_solve_runs_small_problems_on_chip(native):
+    # sc_solve_biharmonic takes the on-chip kernel for problems that fit, so
+    # its result equals the batch call's; the grid solver agrees to kappa tol
+    from paper_2205_03354_amd import stencils
+
+    op = stencils.biharmonic(2)
+    bvp, prob = _problem(33)
+    u1 = torch.zeros_like(prob[1])
+    st1 = native.solve_biharmonic(op, bvp.h, prob[1], u1, g=prob[3], g_halo=bvp.halo)
+    _, st2 = native.solve_biharmonic_batch(op, [prob])
+    assert np.array_equal(u1.cpu().numpy(), prob[2].cpu().numpy())
+    assert st1.iterations == st2[0].iterations and st1.rel_residual == st2[0].rel_residual
+    u3 = torch.zeros_like(prob[1])
+    st3 = native.solve_biharmonic(op, bvp.h, prob[1], u3, g=prob[3], g_halo=bvp.halo, onchip=False)
+    assert st3.rel_residual <= 1e-10
+    a, b = u1.cpu().numpy(), u3.cpu().numpy()
+    assert np.max(np.abs(a - b)) <= 1e-7 * np.max(np.abs(b))

@@ -63,6 +63,18 @@ def test_bvp2d_parity(native, N, prec):
     assert abs(e_gpu - e_or) <= 1e-3 * e_or
 
 
+@pytest.mark.parametrize("N", [33, 65])
+def test_bvp2d_grid_solver_on_small_grids(native, N):
+    # the grid solver itself (small 2D problems otherwise run on chip)
+    bvp, x, st = _gpu_bvp(native, 2, N, native.SC_PREC_F64, onchip=False)
+    op = R.biharmonic(2)
+    b = OP.bvp_rhs(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert OP.true_relres(op, x, b, capi.ZERO_RING, bvp.h) <= 1e-10
+    xo, it, rel_o, rc = OP.bvp_solve(op, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert np.max(np.abs(x - xo)) / np.max(np.abs(xo)) <= 1e-6
+    assert st.iterations > 0 and st.outer >= 1
+
+
 def test_bvp2d_second_order_on_gpu(native):
     errs, hs = [], []
     for N in (17, 33, 65):
