@@ -1,6 +1,6 @@
 // Shared definitions of the gfx950 stencil-composition library: tap
 // patterns, kernel-side weight packs, device scalars of the Krylov solves
-// and the deterministic single-pass grid reduction.
+// and the deterministic two-kernel grid reduction.
 #pragma once
 
 #include <hip/hip_runtime.h>

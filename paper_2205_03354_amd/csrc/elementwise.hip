@@ -1,7 +1,9 @@
 // Element-wise kernels of the Krylov solves (no stencil): the CG update
 // sweep, the refinement cast / update, grid copies and the Cahn-Hilliard
-// diagnostics. All reductions are deterministic (fixed per-thread order,
-// fixed block tree, partials summed in block order by the last block).
+// diagnostics, and the one-block finish kernels of every grid reduction. All
+// reductions are deterministic (fixed per-thread order, fixed block tree,
+// partials summed in slot order by a finish kernel; the diagnostics, run
+// once per call, let their last block sum them).
 #include "internal.hpp"
 
 namespace sc {
