@@ -57,10 +57,17 @@ KERNEL_SOURCES = ["paper_2205_03354_amd/csrc/sweep2d.hpp", "paper_2205_03354_amd
 
 
 def kernel_hash() -> str:
+    """Hash of the apply kernel's sources with comments and blank space
+    removed, so that only a change of code invalidates the counters."""
+    import re
+
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
