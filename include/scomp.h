@@ -278,8 +278,9 @@ sc_status sc_solve_biharmonic(const sc_stencil* op, double h, const sc_grid* f, 
  * sizes. One operator `op` (2D) for all problems; per problem i the spacing
  * h[i], the FP64 grids f[i], u[i] and optionally g[i] (g NULL, or
  * g[i].data NULL, for a zero ring; else halo >= radius), of one shape per
- * problem with n0 n1 <= 4096 and (n0 + 2R)(n1 + 2R) <= 7936 (R the
- * operator's pattern radius; 64 x 64 unknowns for the 13-point L o L).
+ * problem with ceil(n0 / 8) n1 <= 512 and (8 ceil(n0 / 8) + 2R)(n1 + 2R) <= 7936
+ * (R the operator's pattern radius; 64 x 64 unknowns for the 13-point
+ * L o L).
  * From opts: tol and max_iter; precision must be SC_PREC_F64 and precond
  * SC_PC_NONE; check_every and use_graph do not apply. A problem's result
  * does not depend on the rest of the batch. stats (count entries, may be

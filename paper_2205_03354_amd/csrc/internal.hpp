@@ -236,7 +236,7 @@ size_t esize(int dtype);
 
 // On-chip CG for small 2D BVPs, one workgroup per problem (small.hip).
 constexpr int kSmallTaps = 64;
-constexpr int kSmallMaxPoints = 4096;  // unknowns per problem
+constexpr int kSmallMaxPoints = 4096;  // unknowns per problem (512 segments of 8)
 constexpr int kSmallMaxTile = 7936;    // unknowns plus the ring of the pattern radius
 struct SmallDesc {
   const double* f;  // interiors
@@ -259,7 +259,7 @@ struct SmallResult {
   int status;
   int outer;
 };
-// Register class (0..3) of an n0 x n1 problem of pattern radius R, or -1
+// Kernel class (R - 1) of an n0 x n1 problem of pattern radius R, or -1
 // when it does not fit one workgroup.
 int small_class(int64_t n0, int64_t n1, int R);
 // Solve `count` problems of one class (descs and results in device memory).

@@ -1,12 +1,12 @@
 // Batched biharmonic BVPs on small 2D grids (Sec. 3.3), one workgroup per
 // problem with every vector on chip.
 //
-// A grid of up to 4096 unknowns (and 7936 with its ring) fits one workgroup
-// of 512 threads holding up to eight points each in registers (x, r, p, b);
-// the search direction is
-// shared through an LDS tile that carries a zero ring of the stencil's
-// radius, so each iteration is one stencil pass over LDS and two workgroup
-// reductions, with no kernel launches or host round trips. The solve is the
+// A grid of up to 512 row segments of 8 points (4096 unknowns; 7936 values
+// with its ring) fits one workgroup of 512 threads, each holding one segment
+// of x, r, p and b in registers; the search direction is shared through an
+// LDS tile that carries a zero ring of the stencil's radius, so each
+// iteration is one stencil pass over LDS and two workgroup reductions, with
+// no kernel launches or host round trips. The solve is the
 // same textbook CG as the large-grid path: x0 from u, b = f - A g_ring,
 // stop on the recurrence residual, confirm on the true residual b - A x
 // (restarting from it if the check fails), all in FP64. Reductions run in a
@@ -26,9 +26,9 @@ namespace {
 
 constexpr int kNT = 512;
 constexpr int kWaves = kNT / 64;
-constexpr int kMaxPts = 4096;      // unknowns per problem (eight per thread)
+constexpr int kSeg = 8;            // consecutive points of a row per thread
 constexpr int kMaxTile = 7936;     // LDS tile (unknowns plus ring), doubles: 62 KB
-static_assert(kMaxPts == kSmallMaxPoints && kMaxTile == kSmallMaxTile, "limits");
+static_assert(kSeg * kNT == kSmallMaxPoints && kMaxTile == kSmallMaxTile, "limits");
 constexpr int kMaxRestarts = 64;   // true-residual restarts before giving up
 
 // Sum of a and b over the workgroup, in a fixed order, returned to every
@@ -57,48 +57,93 @@ __device__ __forceinline__ void wg_sum2(double& a, double& b, double (*red)[2]) 
   b = sb;
 }
 
-template <int PPT>
+// Thread t owns a segment of kSeg consecutive points of one row (the last
+// segment of a row may be partly empty). The LDS tile has rows of
+// W = ceil(n0 / kSeg) kSeg + 2R doubles, so each segment's stencil reads are
+// 2R + 1 aligned row spans of kSeg + 2R values, loaded once into registers
+// and shared by every tap of that row (a dense (2R+1)^2 weight table, zero
+// where the stencil has no tap).
+// The same for one value.
+__device__ __forceinline__ double wg_sum1(double a, double (*red)[2]) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave][0] = a;
+  __syncthreads();
+  double sa = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) sa += red[w][0];
+  return sa;
+}
+
+template <int R>
 __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restrict__ descs, SmallTaps taps,
                                                        double tol2, long long max_iter,
                                                        SmallResult* __restrict__ results) {
-  __shared__ double tile[kMaxTile];
+  constexpr int D = 2 * R + 1;
+  constexpr int SPAN = kSeg + 2 * R;
+  __shared__ __attribute__((aligned(16))) double tile[kMaxTile];
   __shared__ double red2[2][kWaves][2];
-  __shared__ double sw[kSmallTaps];
-  __shared__ int soff[kSmallTaps];
+  __shared__ double sw[D * D];
   const SmallDesc& d = descs[blockIdx.x];
   const int tid = threadIdx.x;
-  const int R = taps.R;
   const int n0 = d.n0, n1 = d.n1;
-  const int W = n0 + 2 * R;
+  const int spr = (n0 + kSeg - 1) / kSeg;  // segments per row
+  const int W = spr * kSeg + 2 * R;
   const int H = n1 + 2 * R;
-  const int npts = n0 * n1;
-  const int nt = taps.n;
-  if (tid < nt) {
-    sw[tid] = d.w[tid];
-    soff[tid] = taps.dy[tid] * W + taps.dx[tid];
-  }
-  // the ring values of g (zero inside) for b = f - A g_ring
+  for (int i = tid; i < D * D; i += kNT) sw[i] = 0.0;
+  __syncthreads();
+  if (tid < taps.n) sw[(taps.dy[tid] + R) * D + taps.dx[tid] + R] = d.w[tid];
+  // the ring values of g (zero elsewhere) for b = f - A g_ring; g holds a
+  // ring of width R only
   for (int i = tid; i < W * H; i += kNT) {
     const int ty = i / W - R, tx = i % W - R;
-    const bool ring = tx < 0 || tx >= n0 || ty < 0 || ty >= n1;
+    const bool ring = (tx < 0 || tx >= n0 || ty < 0 || ty >= n1) && tx < n0 + R && ty < n1 + R;
     tile[i] = (ring && d.g) ? d.g[(int64_t)ty * d.pg + tx] : 0.0;
   }
   __syncthreads();
 
-  int base[PPT];
-  bool valid[PPT];
-  double x[PPT], r[PPT], p[PPT], b[PPT];
+  const bool seg = tid < spr * n1;
+  const int y = seg ? tid / spr : 0;
+  const int x0 = seg ? (tid % spr) * kSeg : 0;
+  bool valid[kSeg];
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    const int k = tid + j * kNT;
-    valid[j] = k < npts;
-    const int ix = valid[j] ? k % n0 : 0, iy = valid[j] ? k / n0 : 0;
-    base[j] = (iy + R) * W + ix + R;
-    double ag = 0.0;
-#pragma unroll 1
-    for (int t = 0; t < nt; ++t) ag = __builtin_fma(sw[t], tile[base[j] + soff[t]], ag);
-    b[j] = valid[j] ? d.f[(int64_t)iy * d.pf + ix] - ag : 0.0;
-    x[j] = valid[j] ? d.u[(int64_t)iy * d.pu + ix] : 0.0;
+  for (int j = 0; j < kSeg; ++j) valid[j] = seg && x0 + j < n0;
+  const int own = (y + R) * W + x0 + R;  // tile index of point 0 of the segment
+
+  // q = A (tile) at the segment's points
+  auto stencil = [&](double (&q)[kSeg]) {
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) q[j] = 0.0;
+#pragma unroll
+    for (int dy = 0; dy < D; ++dy) {
+      double v[SPAN];
+      const double2* row = reinterpret_cast<const double2*>(tile + (y + dy) * W + x0);
+#pragma unroll
+      for (int k = 0; k < SPAN / 2; ++k) {
+        const double2 t = row[k];
+        v[2 * k] = t.x;
+        v[2 * k + 1] = t.y;
+      }
+#pragma unroll
+      for (int dx = 0; dx < D; ++dx) {
+        const double w = sw[dy * D + dx];
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) q[j] = __builtin_fma(w, v[j + dx], q[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j)
+      if (!valid[j]) q[j] = 0.0;
+  };
+
+  double x[kSeg], r[kSeg], p[kSeg], b[kSeg], q[kSeg];
+  stencil(q);  // A g_ring
+#pragma unroll
+  for (int j = 0; j < kSeg; ++j) {
+    const int64_t gx = x0 + j;
+    b[j] = valid[j] ? d.f[(int64_t)y * d.pf + gx] - q[j] : 0.0;
+    x[j] = valid[j] ? d.u[(int64_t)y * d.pu + gx] : 0.0;
   }
   __syncthreads();
   // the Krylov vectors see a zero ring
@@ -106,38 +151,30 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
   __syncthreads();
 
   int rb = 0;  // the reduction buffer of the next wg_sum2
-  auto reduce2 = [&](double& a, double& b) {
-    wg_sum2(a, b, red2[rb]);
+  auto reduce2 = [&](double& a, double& c) {
+    wg_sum2(a, c, red2[rb]);
     rb ^= 1;
   };
-  // q = A v at this thread's points, v given in registers (taps outer,
-  // points inner: one accumulator per point). Every call is followed by a
-  // reduction, whose barrier orders these tile reads before the next writes.
-  auto apply = [&](const double (&v)[PPT], double (&q)[PPT]) {
+  auto reduce1 = [&](double a) {
+    const double t = wg_sum1(a, red2[rb]);
+    rb ^= 1;
+    return t;
+  };
+  // q = A v for v in registers. Every call is followed by a reduction,
+  // whose barrier orders these tile reads before the next writes.
+  auto apply = [&](const double (&v)[kSeg], double (&out)[kSeg]) {
 #pragma unroll
-    for (int j = 0; j < PPT; ++j)
-      if (valid[j]) tile[base[j]] = v[j];
+    for (int j = 0; j < kSeg; ++j)
+      if (valid[j]) tile[own + j] = v[j];
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) q[j] = 0.0;
-#pragma unroll 1
-    for (int t = 0; t < nt; ++t) {
-      const double wt = sw[t];
-      const int o = soff[t];
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) q[j] = __builtin_fma(wt, tile[base[j] + o], q[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < PPT; ++j)
-      if (!valid[j]) q[j] = 0.0;
+    stencil(out);
   };
 
-  double q[PPT];
   // true residual r = b - A x, <r, r>, <b, b>
   apply(x, q);
   double rr = 0.0, bb = 0.0;
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) {
+  for (int j = 0; j < kSeg; ++j) {
     r[j] = b[j] - q[j];
     p[j] = r[j];
     rr += r[j] * r[j];
@@ -155,10 +192,10 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
       break;
     }
     apply(p, q);
-    double pq = 0.0, unused = 0.0;
+    double pq = 0.0;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) pq += p[j] * q[j];
-    reduce2(pq, unused);
+    for (int j = 0; j < kSeg; ++j) pq += p[j] * q[j];
+    pq = reduce1(pq);
     if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
       status = SC_EBREAKDOWN;
       break;
@@ -166,24 +203,24 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
     const double alpha = rr / pq;
     double rn = 0.0;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
+    for (int j = 0; j < kSeg; ++j) {
       x[j] = __builtin_fma(alpha, p[j], x[j]);
       r[j] = __builtin_fma(-alpha, q[j], r[j]);
       rn += r[j] * r[j];
     }
-    reduce2(rn, unused);
+    rn = reduce1(rn);
     ++it;
     if (rn <= rr_stop) {
       // confirm on the true residual; restart the recurrence from it if not
       apply(x, q);
       double rt = 0.0;
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
+      for (int j = 0; j < kSeg; ++j) {
         r[j] = b[j] - q[j];
         p[j] = r[j];
         rt += r[j] * r[j];
       }
-      reduce2(rt, unused);
+      rt = reduce1(rt);
       rr_true = rt;
       ++outer;
       if (rt <= rr_stop) {
@@ -197,27 +234,24 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
     }
     const double beta = rn / rr;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) p[j] = __builtin_fma(beta, p[j], r[j]);
+    for (int j = 0; j < kSeg; ++j) p[j] = __builtin_fma(beta, p[j], r[j]);
     rr = rn;
   }
   if (status != SC_OK) {
     // the true residual of the returned iterate
     apply(x, q);
-    double rt = 0.0, unused = 0.0;
+    double rt = 0.0;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
+    for (int j = 0; j < kSeg; ++j) {
       const double e = b[j] - q[j];
       rt += e * e;
     }
-    reduce2(rt, unused);
+    rt = reduce1(rt);
     rr_true = rt;
   }
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    if (!valid[j]) continue;
-    const int k = tid + j * kNT;
-    d.u[(int64_t)(k / n0) * d.pu + k % n0] = x[j];
-  }
+  for (int j = 0; j < kSeg; ++j)
+    if (valid[j]) d.u[(int64_t)y * d.pu + x0 + j] = x[j];
   if (tid == 0) {
     SmallResult& o = results[blockIdx.x];
     o.iter = it;
@@ -231,20 +265,22 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
 }  // namespace
 
 int small_class(int64_t n0, int64_t n1, int R) {
-  if (n0 < 1 || n1 < 1 || n0 * n1 > kMaxPts || (n0 + 2 * R) * (n1 + 2 * R) > kMaxTile) return -1;
-  const int64_t pts = n0 * n1;
-  return pts <= kNT ? 0 : pts <= 2 * kNT ? 1 : pts <= 4 * kNT ? 2 : 3;
+  if (n0 < 1 || n1 < 1 || R < 1 || R > 4) return -1;
+  const int64_t spr = (n0 + kSeg - 1) / kSeg;
+  if (spr * n1 > kNT || (spr * kSeg + 2 * R) * (n1 + 2 * R) > kMaxTile) return -1;
+  return R - 1;
 }
 
 hipError_t launch_small_cg(const SmallDesc* descs, const SmallTaps& taps, int count, int cls, double tol2,
                            long long max_iter, SmallResult* results, hipStream_t st) {
   if (count < 1) return hipSuccess;
+  if (cls != taps.R - 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)count), block(kNT);
   switch (cls) {
     case 0: hipLaunchKernelGGL(small_cg_kernel<1>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
     case 1: hipLaunchKernelGGL(small_cg_kernel<2>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
-    case 2: hipLaunchKernelGGL(small_cg_kernel<4>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
-    case 3: hipLaunchKernelGGL(small_cg_kernel<8>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
+    case 2: hipLaunchKernelGGL(small_cg_kernel<3>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
+    case 3: hipLaunchKernelGGL(small_cg_kernel<4>, grid, block, 0, st, descs, taps, tol2, max_iter, results); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -309,8 +345,8 @@ sc_status solve_biharmonic_batch(const sc_stencil* op, const double* h, int32_t 
     const int64_t n0 = u[i].n[0], n1 = u[i].n[1];
     const int R = ks.R;
     if (small_class(n0, n1, R) < 0) {
-      set_error("problem %d: %lld x %lld unknowns exceed the on-chip limit (%d unknowns, %d with the ring)", i,
-                (long long)n0, (long long)n1, kMaxPts, kMaxTile);
+      set_error("problem %d: %lld x %lld unknowns do not fit one workgroup (at most %d rows of %d-point segments, "
+                "%d values with the ring)", i, (long long)n0, (long long)n1, kNT, kSeg, kMaxTile);
       return SC_EUNSUPPORTED;
     }
     if (gi && gi->halo < R) {
