@@ -109,7 +109,7 @@ struct alignas(64) DevScalars {
   double scale;     // refinement scale s = ||r||
   long long iter;   // iterations performed
   int done;         // 0 running, 1 recurrence converged, 2 breakdown
-  unsigned int unused;
+  int slots;        // partial sums written by the last direction sweep
   double rz;        // preconditioned CG: <r, M^-1 r>
   double pad[4];
 };
@@ -185,8 +185,9 @@ __device__ __forceinline__ double sum_partials(const double* partials, int n) {
 }
 
 // What the finish kernel does with the total.
+// (The direction sweep's <p, Ap> has no finish kernel: the CG update that
+// follows it sums those partials itself.)
 enum FinKind : int {
-  FIN_CGDIR = 0,   // pq; alpha = (flag ? rz : rr) / pq, breakdown check
   FIN_RESID = 1,   // rr_true (flag: also restart the recurrence: rr, beta, done)
   FIN_RHS = 2,     // bb; rr_stop = c bb
   FIN_UPDATE = 3,  // iteration count, convergence, beta, rr

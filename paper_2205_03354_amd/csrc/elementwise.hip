@@ -31,9 +31,30 @@ template <typename T>
 __global__ void __launch_bounds__(kNT)
     cg_update_kernel(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
                      const T* __restrict__ q, int64_t pitch, int64_t zpitch, int64_t n0, int64_t n1,
-                     int64_t n2, DevScalars* s, double* partials) {
+                     int64_t n2, DevScalars* s, const double* __restrict__ pq_partials, int pc,
+                     double* partials) {
   if (s->done) return;
-  const T alpha = (T)s->alpha;
+  // alpha = (pc ? <r, z> : <r, r>) / <p, q> from the direction sweep's
+  // partials: every block sums them in the same order, so all agree; block
+  // 0 records pq and alpha, or the breakdown
+  __shared__ double s_alpha;
+  __shared__ int s_ok;
+  const double pq = sum_partials<kNT>(pq_partials, s->slots);
+  if (threadIdx.x == 0) {
+    const bool ok = pq > 0.0 && __builtin_isfinite(pq);
+    s_ok = ok ? 1 : 0;
+    s_alpha = ok ? (pc ? s->rz : s->rr) / pq : 0.0;
+    if (blockIdx.x == 0) {
+      s->pq = pq;
+      if (ok)
+        s->alpha = s_alpha;
+      else
+        s->done = 2;
+    }
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  const T alpha = (T)s_alpha;
   const RowRange rr = block_rows(n1 * n2);
   double dot = 0.0;
   for (int64_t rho = rr.r0; rho < rr.r1; ++rho) {
@@ -319,13 +340,7 @@ __global__ void __launch_bounds__(kNT) finish_kernel(FinArgs f) {
   if (f.skip_if_done && s->done) return;
   const double total = sum_partials<kNT>(f.partials, f.n);
   if (threadIdx.x != 0) return;
-  if constexpr (FK == FIN_CGDIR) {
-    s->pq = total;
-    if (!(total > 0.0) || !__builtin_isfinite(total))
-      s->done = 2;
-    else
-      s->alpha = (f.flag ? s->rz : s->rr) / total;  // flag: preconditioned, alpha = <r, z> / <p, A p>
-  } else if constexpr (FK == FIN_RESID) {
+  if constexpr (FK == FIN_RESID) {
     s->rr_true = total;
     if (f.flag) {
       s->rr = total;
@@ -363,7 +378,6 @@ __global__ void __launch_bounds__(kNT) finish_kernel(FinArgs f) {
 
 hipError_t launch_finish(int fk, const FinArgs& f, hipStream_t st) {
   switch (fk) {
-    case FIN_CGDIR: hipLaunchKernelGGL(finish_kernel<FIN_CGDIR>, dim3(1), dim3(kNT), 0, st, f); break;
     case FIN_RESID: hipLaunchKernelGGL(finish_kernel<FIN_RESID>, dim3(1), dim3(kNT), 0, st, f); break;
     case FIN_RHS: hipLaunchKernelGGL(finish_kernel<FIN_RHS>, dim3(1), dim3(kNT), 0, st, f); break;
     case FIN_UPDATE: hipLaunchKernelGGL(finish_kernel<FIN_UPDATE>, dim3(1), dim3(kNT), 0, st, f); break;
@@ -438,17 +452,17 @@ hipError_t launch_pc_dot(int dtype, const void* r, const void* z, const Layout& 
 }
 
 hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
-                            const Layout& lay, const int64_t* n, DevScalars* s, double* partials,
-                            hipStream_t st) {
+                            const Layout& lay, const int64_t* n, DevScalars* s, const double* pq_partials,
+                            int pc, double* partials, hipStream_t st) {
   const int nb = elem_blocks(n);
   if (dtype == SC_F64) {
     hipLaunchKernelGGL(cg_update_kernel<double>, dim3(nb), dim3(kNT), 0, st, (double*)x, (double*)r,
                        (const double*)p, (const double*)q, lay.pitch, lay.zpitch, n[0], n[1], n[2], s,
-                       partials);
+                       pq_partials, pc, partials);
   } else {
     hipLaunchKernelGGL(cg_update_kernel<float>, dim3(nb), dim3(kNT), 0, st, (float*)x, (float*)r,
                        (const float*)p, (const float*)q, lay.pitch, lay.zpitch, n[0], n[1], n[2], s,
-                       partials);
+                       pq_partials, pc, partials);
   }
   return finish(FIN_UPDATE, s, partials, nb, 0.0, 0, 1, st);
 }

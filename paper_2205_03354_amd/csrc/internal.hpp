@@ -137,9 +137,13 @@ constexpr int kElemBlocks = 1024;  // blocks of the element-wise kernels
 // partials of the kernel launched just before on `st` and finalises.
 hipError_t launch_finish(int fk, const FinArgs& f, hipStream_t st);
 
+// x += alpha p; r -= alpha q; <r, r> -> beta and the stop test, with
+// alpha = (pc ? rz : rr) / <p, q> formed by every block from the s->slots
+// partials of the direction sweep just before (pq_partials must differ from
+// partials).
 hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
-                            const Layout& lay, const int64_t* n, DevScalars* s, double* partials,
-                            hipStream_t st);
+                            const Layout& lay, const int64_t* n, DevScalars* s, const double* pq_partials,
+                            int pc, double* partials, hipStream_t st);
 // r32 = r64 / s; d32 = 0; rr = <r32, r32>, rr_stop = inner_tol^2 rr. A
 // restart (keep_direction 0) sets s = sqrt(s64->rr_true) and beta = 0; a
 // reliable update (keep_direction 1) keeps s and rescales beta so that the

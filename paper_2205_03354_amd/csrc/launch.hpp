@@ -166,12 +166,13 @@ Taps<T, sym_num_classes(PAT, R)> make_sym_taps(const KStencil& ks) {
 }
 
 // The finish kernel of a sweep that reduces a dot product (after the sweep's
-// own launch on the same stream).
+// own launch on the same stream). The direction sweep has none: the CG
+// update that always follows it sums its partials into alpha.
 template <int KIND>
 hipError_t finish_sweep(const DevScalars* scal, const double* partials, int blocks, double c2, int flag,
                         hipStream_t st) {
   const hipError_t e = hipGetLastError();
-  if constexpr (!kind_has_dot(KIND)) {
+  if constexpr (!kind_has_dot(KIND) || KIND == K_CGDIR) {
     return e;
   } else {
     if (e != hipSuccess) return e;
@@ -181,8 +182,7 @@ hipError_t finish_sweep(const DevScalars* scal, const double* partials, int bloc
     f.n = blocks;
     f.c = c2;
     f.flag = flag;
-    f.skip_if_done = KIND == K_CGDIR ? 1 : 0;
-    const int fk = KIND == K_CGDIR ? FIN_CGDIR : (KIND == K_RESID ? FIN_RESID : FIN_RHS);
+    const int fk = KIND == K_RESID ? FIN_RESID : FIN_RHS;
     return launch_finish(fk, f, st);
   }
 }

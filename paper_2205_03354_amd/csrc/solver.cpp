@@ -270,6 +270,7 @@ sc_status SolveTask::init(const TaskSpec& spec, hipStream_t st) {
   d64_ = static_cast<DevScalars*>(dev_block_);
   d32s_ = d64_ + 1;
   partials_ = reinterpret_cast<double*>(static_cast<char*>(dev_block_) + 2 * sizeof(DevScalars) + 256);
+  upd_partials_ = partials_ + slots;  // the update's partials (room for 3 x slots)
   sc_status s;
   if ((s = make(&x_, SC_F64)) != SC_OK || (s = make(&b_, SC_F64)) != SC_OK || (s = make(&r64_, SC_F64)) != SC_OK)
     return s;
@@ -395,7 +396,7 @@ sc_status SolveTask::enqueue_block(bool f32) {
                         q_.base, r.lay, 0, 0, 0, 0, ds);
     if (s != SC_OK) return s;
     SC_HIP_CHECK(launch_cg_update(dtype, x.base, r.base, p_[1 - cur_].base, q_.base, x.lay, spec_.n, ds, partials_,
-                                  st_));
+                                  0, upd_partials_, st_));
     cur_ = 1 - cur_;
     return SC_OK;
   };
@@ -410,7 +411,7 @@ sc_status SolveTask::enqueue_block(bool f32) {
                           q_.base, r.lay, 1, 0, 0, 0, ds);
       if (s != SC_OK) return s;
       SC_HIP_CHECK(launch_cg_update(dtype, x.base, r.base, p_[1 - cur_].base, q_.base, x.lay, spec_.n, ds,
-                                    partials_, st_));
+                                    partials_, 1, upd_partials_, st_));
       cur_ = 1 - cur_;
       if ((s = precondition(f32, 0)) != SC_OK) return s;
     }

@@ -237,6 +237,8 @@ __global__ void __launch_bounds__(NT)
   }
 
   if constexpr (HAS_DOT) block_partial<NT>(dot, tile, a.partials);
+  if constexpr (KIND == K_CGDIR)
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.scal->slots = (int)gridDim.x;
 }
 
 }  // namespace sc

@@ -419,6 +419,8 @@ __global__ void __launch_bounds__(64)
     body(std::integral_constant<bool, false>{});
 
   if constexpr (HAS_DOT) block_partial<64>(dot, tile, a.partials);
+  if constexpr (KIND == K_CGDIR)
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.scal->slots = (int)gridDim.x;
 }
 
 }  // namespace sc

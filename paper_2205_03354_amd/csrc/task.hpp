@@ -125,6 +125,7 @@ class SolveTask {
   DevScalars* h64_ = nullptr;
   DevScalars* h32_ = nullptr;
   double* partials_ = nullptr;
+  double* upd_partials_ = nullptr;  // the CG update's partials (the sweep's stay readable)
   void* dev_block_ = nullptr;
   std::vector<void*> allocs_;
   size_t bytes_ = 0;
