@@ -75,7 +75,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + "\n".join(r[1] for r in failed))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + [u[1] for u in units] + \
-        ["-L/opt/rocm/lib", "-lrocblas", "-lrocsparse", "-Wl,-rpath,/opt/rocm/lib"]
+        ["-L/opt/rocm/lib", "-lrocblas", "-lrocsparse", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stderr)

@@ -7,18 +7,63 @@
 // L_D is diagonalised by the orthonormal sine transform S (S = S^T = S^-1)
 // along every axis, so M^-1 = L_D^-2 = S (Lambda^-2 o (S r)) with Lambda the
 // sums of the 1D eigenvalues -(4/h^2) sin^2(pi k / (2(n+1))). Each axis
-// transform is a dense product with the n x n matrix S (a GEMM on the
-// interior, batched over planes or rows), done by rocBLAS; the scaling is a
-// library kernel.
+// transform is either a dense product with the n x n matrix S (a GEMM on the
+// interior, batched over planes or rows, by rocBLAS: 3D grids and small or
+// FFT-unfriendly 2D ones) or, on 2D grids of side >= kFftMinSide whose
+// n + 1 factors into 2, 3, 5 and 7, a real FFT (rocFFT) of each row's odd
+// extension, O(n log n) per row and bandwidth-bound, written transposed so
+// that the second axis is again a row transform; the extension, extraction
+// and scaling are library kernels.
 #include <rocblas/rocblas.h>
+#include <rocfft/rocfft.h>
 
+#include <array>
 #include <map>
+#include <mutex>
 
 #include "task.hpp"
 
 namespace sc {
 
 namespace {
+
+// Odd extension of each row: e = (0, v_1 .. v_n, 0, -v_n .. -v_1), length
+// N = 2 (n + 1); its real FFT at k = 1 .. n is -2i sum_j v_j sin(pi j k / (n + 1)).
+template <typename T>
+__global__ void __launch_bounds__(256) dst_extend_kernel(const T* __restrict__ v, int64_t pv, int64_t n, int64_t m,
+                                                         T* __restrict__ e) {
+  const int64_t N = 2 * (n + 1);
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m * N; i += stride) {
+    const int64_t r = i / N, j = i - r * N;
+    T x = T(0);
+    if (j >= 1 && j <= n)
+      x = v[r * pv + j - 1];
+    else if (j > n + 1)
+      x = -v[r * pv + (N - j) - 1];
+    e[i] = x;
+  }
+}
+
+// out[k - 1][r] = -c Im(F[r][k]) / 2 for k = 1 .. n (transposed through a
+// 32 x 32 LDS tile so that reads and writes are both coalesced).
+template <typename T>
+__global__ void __launch_bounds__(256) dst_extract_kernel(const T* __restrict__ F, int64_t n, int64_t m, T* out,
+                                                          int64_t pout, T c) {
+  __shared__ T tile[32][33];
+  const int64_t H = n + 2;  // complex values per row of the half spectrum
+  const int64_t k0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t r = r0 + yy, k = k0 + tx + 1;
+    tile[yy][tx] = (r < m && k <= n) ? F[2 * (r * H + k) + 1] : T(0);
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t k = k0 + yy + 1, r = r0 + tx;
+    if (k <= n && r < m) out[(k - 1) * pout + r] = -T(0.5) * c * tile[tx][yy];
+  }
+}
 
 rocblas_handle blas_handle() {
   thread_local std::map<int, rocblas_handle> handles;
@@ -57,11 +102,35 @@ sc_status gemm(rocblas_handle hb, int dtype, int64_t m, int64_t n, int64_t k, co
   return SC_OK;
 }
 
+// The FFT path is taken when both odd-extension lengths 2 (n + 1) factor
+// into 2, 3, 5 and 7 (sizes with precompiled FFT kernels); others keep the
+// GEMM transforms.
+bool fft_sides(int dim, const int64_t* n) {
+  if (dim != 2) return false;
+  for (int a = 0; a < 2; ++a) {
+    if (n[a] < kFftMinSide) return false;
+    int64_t v = n[a] + 1;
+    for (int64_t f : {2, 3, 5, 7})
+      while (v % f == 0) v /= f;
+    if (v != 1) return false;
+  }
+  return true;
+}
+
 }  // namespace
 
 size_t fastpoisson_bytes(int dim, const int64_t* n, int dtype) {
   const size_t es = dtype == SC_F64 ? 8 : 4;
   size_t b = 0;
+  if (fft_sides(dim, n)) {
+    // extension, half spectrum and transposed field (the FFT work buffers are
+    // small next to these)
+    const size_t m = (size_t)std::max(n[0], n[1]);
+    const size_t nn = (size_t)std::max(n[0], n[1]);
+    b += m * (2 * nn + 2) * es + m * (nn + 2) * 2 * es + (size_t)(n[0] * n[1]) * es + 4 * 1048576;
+    for (int a = 0; a < dim; ++a) b += (((size_t)n[a] * 8 + 4095) & ~(size_t)4095);
+    return b;
+  }
   for (int a = 0; a < dim; ++a) {
     bool dup = false;
     for (int c = 0; c < a; ++c) dup = dup || n[c] == n[a];
@@ -72,7 +141,114 @@ size_t fastpoisson_bytes(int dim, const int64_t* n, int dtype) {
 }
 
 FastPoisson::~FastPoisson() {
+  for (Dst* d : {&dx_, &dy_})
+    if (d->info) rocfft_execution_info_destroy(static_cast<rocfft_execution_info>(d->info));
   for (void* p : allocs_) pool_free(p);
+}
+
+sc_status FastPoisson::dst_init(Dst* d, int64_t n, int64_t m, hipStream_t st) {
+  // Plans are built once per (device, length, batch, precision) and kept for
+  // the life of the process: building one costs milliseconds, more than a
+  // whole preconditioned solve on a mid-size grid. Each preconditioner keeps
+  // its own execution info (stream) and work buffer.
+  static std::mutex mu;
+  static std::map<std::array<int64_t, 4>, rocfft_plan> plans;
+  static bool setup_done = false;
+  int dev = 0;
+  SC_HIP_CHECK(hipGetDevice(&dev));
+  d->n = n;
+  d->m = m;
+  rocfft_plan plan = nullptr;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if (!setup_done) {
+      if (rocfft_setup() != rocfft_status_success) {
+        set_error("rocFFT setup failed");
+        return SC_EDEVICE;
+      }
+      setup_done = true;
+    }
+    const std::array<int64_t, 4> key{dev, n, m, dtype_};
+    auto it = plans.find(key);
+    if (it != plans.end()) {
+      plan = it->second;
+    } else {
+      const size_t len = (size_t)(2 * (n + 1));
+      const rocfft_status e =
+          rocfft_plan_create(&plan, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
+                             dtype_ == SC_F64 ? rocfft_precision_double : rocfft_precision_single, 1, &len,
+                             (size_t)m, nullptr);
+      if (e != rocfft_status_success) {
+        set_error("rocFFT plan creation failed (status %d)", (int)e);
+        return SC_EDEVICE;
+      }
+      plans[key] = plan;
+    }
+  }
+  d->plan = plan;
+  rocfft_execution_info info = nullptr;
+  if (rocfft_execution_info_create(&info) != rocfft_status_success) {
+    set_error("rocFFT execution info creation failed");
+    return SC_EDEVICE;
+  }
+  d->info = info;
+  size_t wb = 0;
+  if (rocfft_plan_get_work_buffer_size(plan, &wb) != rocfft_status_success) {
+    set_error("rocFFT work buffer query failed");
+    return SC_EDEVICE;
+  }
+  if (wb > 0) {
+    void* w = pool_alloc(wb);
+    if (!w) {
+      set_error("rocFFT work buffer allocation failed");
+      return SC_ENOMEM;
+    }
+    allocs_.push_back(w);
+    d->work = w;
+    d->work_bytes = wb;
+    if (rocfft_execution_info_set_work_buffer(info, w, wb) != rocfft_status_success) {
+      set_error("rocFFT work buffer binding failed");
+      return SC_EDEVICE;
+    }
+  }
+  (void)st;
+  return SC_OK;
+}
+
+sc_status FastPoisson::dst_rows(const Dst& d, const void* in, int64_t pin, void* out, int64_t pout,
+                                hipStream_t st) const {
+  const int64_t n = d.n, m = d.m, N = 2 * (n + 1);
+  const int64_t total = m * N;
+  const unsigned eb = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+  const double c = std::sqrt(2.0 / (double)(n + 1));
+  const dim3 tgrid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
+  if (dtype_ == SC_F64)
+    hipLaunchKernelGGL(dst_extend_kernel<double>, dim3(eb), dim3(256), 0, st, static_cast<const double*>(in), pin, n,
+                       m, static_cast<double*>(ext_));
+  else
+    hipLaunchKernelGGL(dst_extend_kernel<float>, dim3(eb), dim3(256), 0, st, static_cast<const float*>(in), pin, n,
+                       m, static_cast<float*>(ext_));
+  SC_HIP_CHECK(hipGetLastError());
+  auto info = static_cast<rocfft_execution_info>(d.info);
+  if (rocfft_execution_info_set_stream(info, st) != rocfft_status_success) {
+    set_error("rocFFT stream binding failed");
+    return SC_EDEVICE;
+  }
+  void* ib[1] = {ext_};
+  void* ob[1] = {spec_};
+  const rocfft_status e = rocfft_execute(static_cast<rocfft_plan>(d.plan), ib, ob, info);
+  if (e != rocfft_status_success) {
+    set_error("rocFFT execution failed (status %d)", (int)e);
+    return SC_EDEVICE;
+  }
+  if (dtype_ == SC_F64)
+    hipLaunchKernelGGL(dst_extract_kernel<double>, tgrid, dim3(256), 0, st, static_cast<const double*>(spec_), n, m,
+                       static_cast<double*>(out), pout, c);
+  else
+    hipLaunchKernelGGL(dst_extract_kernel<float>, tgrid, dim3(256), 0, st, static_cast<const float*>(spec_), n, m,
+                       static_cast<float*>(out), pout, (float)c);
+  SC_HIP_CHECK(hipGetLastError());
+  return SC_OK;
 }
 
 sc_status FastPoisson::init(int dim, const int64_t* n, double h, int dtype, hipStream_t st) {
@@ -80,6 +256,32 @@ sc_status FastPoisson::init(int dim, const int64_t* n, double h, int dtype, hipS
   dtype_ = dtype;
   for (int a = 0; a < 3; ++a) n_[a] = a < dim ? n[a] : 1;
   const size_t es = dtype == SC_F64 ? 8 : 4;
+  fft_ = fft_sides(dim, n_);
+  if (fft_) {
+    sc_status e;
+    const int64_t mx = std::max(n_[0], n_[1]);
+    ext_ = pool_alloc((size_t)(mx * (2 * mx + 2)) * es);
+    spec_ = pool_alloc((size_t)(mx * (mx + 2)) * 2 * es);
+    tr_ = pool_alloc((size_t)(n_[0] * n_[1]) * es);
+    for (void* q : {ext_, spec_, tr_})
+      if (q) allocs_.push_back(q);
+    if (!ext_ || !spec_ || !tr_) {
+      set_error("preconditioner allocation failed");
+      return SC_ENOMEM;
+    }
+    if ((e = dst_init(&dx_, n_[0], n_[1], st)) != SC_OK || (e = dst_init(&dy_, n_[1], n_[0], st)) != SC_OK) return e;
+    for (int a = 0; a < 2; ++a) {
+      void* l = pool_alloc((size_t)n_[a] * 8);
+      if (!l) {
+        set_error("preconditioner allocation failed");
+        return SC_ENOMEM;
+      }
+      allocs_.push_back(l);
+      lam_[a] = static_cast<double*>(l);
+      SC_HIP_CHECK(launch_pc_init(dtype, nullptr, lam_[a], n_[a], h, st));
+    }
+    return SC_OK;
+  }
   for (int a = 0; a < dim; ++a) {
     int same = -1;
     for (int c = 0; c < a; ++c)
@@ -117,6 +319,15 @@ sc_status FastPoisson::apply(const void* r, void* z, void* tmp, const Layout& la
   sc_status e;
   const int64_t n0 = n_[0], n1 = n_[1], n2 = n_[2];
   const int64_t p = lay.pitch, zp = lay.zpitch;
+  if (fft_) {
+    // along x (rows of r) into tr (transposed), along y back into tmp; scale;
+    // the same two transforms again into z
+    if ((e = dst_rows(dx_, r, p, tr_, n1, st)) != SC_OK || (e = dst_rows(dy_, tr_, n1, tmp, p, st)) != SC_OK)
+      return e;
+    SC_HIP_CHECK(launch_pc_scale(dtype_, tmp, lay, n_, lam_[0], lam_[1], nullptr, s, st));
+    if ((e = dst_rows(dx_, tmp, p, tr_, n1, st)) != SC_OK) return e;
+    return dst_rows(dy_, tr_, n1, z, p, st);
+  }
   // one sine transform along every axis, in -> out (in and out distinct)
   auto transform = [&](const void* in, void* out, void* mid) -> sc_status {
     sc_status r2;

@@ -58,6 +58,24 @@ class FastPoisson {
   sc_status apply(const void* r, void* z, void* tmp, const Layout& lay, const DevScalars* s, hipStream_t st) const;
 
  private:
+  // One sine transform along the rows of `in` (m rows of n, row pitch pin),
+  // written transposed into `out` (n rows of m, row pitch pout), by a real
+  // FFT of the odd extension (2D grids of side >= kFftMinSide with 7-smooth
+  // n + 1).
+  struct Dst {
+    int64_t n = 0, m = 0;
+    void* plan = nullptr;  // rocfft_plan
+    void* info = nullptr;  // rocfft_execution_info
+    void* work = nullptr;
+    size_t work_bytes = 0;
+  };
+  sc_status dst_init(Dst* d, int64_t n, int64_t m, hipStream_t st);
+  sc_status dst_rows(const Dst& d, const void* in, int64_t pin, void* out, int64_t pout, hipStream_t st) const;
+  bool fft_ = false;
+  Dst dx_, dy_;          // along x (n0, batch n1) and along y (n1, batch n0)
+  void* ext_ = nullptr;  // odd extensions, max m (2n + 2) reals
+  void* spec_ = nullptr; // their half spectra, max m (n + 2) complex
+  void* tr_ = nullptr;   // the x-transformed field, transposed (n0 rows of n1)
   int dim_ = 2;
   int dtype_ = SC_F64;
   int64_t n_[3] = {1, 1, 1};
@@ -66,6 +84,7 @@ class FastPoisson {
   std::vector<void*> allocs_;
 };
 size_t fastpoisson_bytes(int dim, const int64_t* n, int dtype);
+constexpr int64_t kFftMinSide = 200;  // 2D sides from which the transforms may use FFTs
 
 class SolveTask {
  public:
