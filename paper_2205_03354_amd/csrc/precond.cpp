@@ -10,7 +10,7 @@
 // transform is either a dense product with the n x n matrix S (a GEMM on the
 // interior, batched over planes or rows, by rocBLAS: 3D grids and small or
 // FFT-unfriendly 2D ones) or, on 2D grids of side >= kFftMinSide whose
-// n + 1 factors into 2, 3, 5 and 7, a real FFT (rocFFT) of each row's odd
+// n + 1 is a power of two, a real FFT (rocFFT) of each row's odd
 // extension, O(n log n) per row and bandwidth-bound, written transposed so
 // that the second axis is again a row transform; the extension, extraction
 // and scaling are library kernels.
@@ -102,17 +102,16 @@ sc_status gemm(rocblas_handle hb, int dtype, int64_t m, int64_t n, int64_t k, co
   return SC_OK;
 }
 
-// The FFT path is taken when both odd-extension lengths 2 (n + 1) factor
-// into 2, 3, 5 and 7 (sizes with precompiled FFT kernels); others keep the
-// GEMM transforms.
+// The FFT path is taken when both odd-extension lengths 2 (n + 1) are
+// powers of two: those have precompiled FFT kernels, so a plan builds in
+// milliseconds; other lengths may need kernels compiled at run time (a cost
+// a request stream of arbitrary sizes cannot pay), and keep the GEMM
+// transforms.
 bool fft_sides(int dim, const int64_t* n) {
   if (dim != 2) return false;
   for (int a = 0; a < 2; ++a) {
-    if (n[a] < kFftMinSide) return false;
-    int64_t v = n[a] + 1;
-    for (int64_t f : {2, 3, 5, 7})
-      while (v % f == 0) v /= f;
-    if (v != 1) return false;
+    const int64_t v = n[a] + 1;
+    if (n[a] < kFftMinSide || (v & (v - 1)) != 0) return false;
   }
   return true;
 }

@@ -60,8 +60,8 @@ class FastPoisson {
  private:
   // One sine transform along the rows of `in` (m rows of n, row pitch pin),
   // written transposed into `out` (n rows of m, row pitch pout), by a real
-  // FFT of the odd extension (2D grids of side >= kFftMinSide with 7-smooth
-  // n + 1).
+  // FFT of the odd extension (2D grids of side >= kFftMinSide with n + 1 a
+  // power of two).
   struct Dst {
     int64_t n = 0, m = 0;
     void* plan = nullptr;  // rocfft_plan
