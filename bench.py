@@ -382,8 +382,10 @@ def serve_bench(native, torch, n_req: int):
 
 def varcoef_bench(native, torch, reps: int = 20):
     """div(M grad(Lap x)) on the 4097^2 FP64 periodic grid with a varying
-    mobility: two terms, each a pointwise-scaled inner sweep into a
-    workspace and an outer sweep (sc_apply_varcoef)."""
+    mobility (sc_apply_varcoef), in both forms: the fused 2D kernel (x and M
+    staged once per tile, w = M * A_t(x) kept in LDS) and the two-sweep form
+    (per term, an inner sweep scaled by M into a workspace and an outer
+    sweep)."""
     import synthetic as S
     from paper_2205_03354_amd import stencils
 
@@ -394,20 +396,29 @@ def varcoef_bench(native, torch, reps: int = 20):
     x = torch.from_numpy(S.uniform_field((n, n), seed=0)).to(dev)
     M = 1.0 + 0.5 * torch.from_numpy(S.uniform_field((n, n), seed=1)).to(dev)
     y = torch.empty_like(x)
-    for _ in range(3):
-        native.apply_varcoef(terms, M, x, y, native.SC_BC_PERIODIC, h=h)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        native.apply_varcoef(terms, M, x, y, native.SC_BC_PERIODIC, h=h)
-    dt = (time.perf_counter() - t0) / reps
     pts = float(n) * n
-    return {"workload": "div(M grad(Lap x)), 4097^2 FP64 periodic, M = 1 + U[-0.5,0.5]; terms "
-                        "(D1_a o L5, D1_a), a = x, y",
-            "ms_per_apply": round(dt * 1e3, 3),
-            "gbs_vs_fused_minimum": round(24.0 * pts / dt / 1e9, 1),
-            "gbs_moved": round(88.0 * pts / dt / 1e9, 1),
-            "note": "fused minimum = read x and M, write y (24 B/pt); the two-sweep form moves 11 words/pt"}
+    out = {"workload": "div(M grad(Lap x)), 4097^2 FP64 periodic, M = 1 + U[-0.5,0.5]; terms "
+                       "(D1_a o L5, D1_a), a = x, y",
+           "note": "minimum traffic = read x and M, write y (24 B/pt); the two-sweep form moves 11 words/pt"}
+    saved = os.environ.pop("SCOMP_VARCOEF", None)
+    try:
+        for form in ("fused", "twosweep"):
+            if form == "twosweep":
+                os.environ["SCOMP_VARCOEF"] = "twosweep"
+            for _ in range(3):
+                native.apply_varcoef(terms, M, x, y, native.SC_BC_PERIODIC, h=h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                native.apply_varcoef(terms, M, x, y, native.SC_BC_PERIODIC, h=h)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            out[form] = {"ms_per_apply": round(dt * 1e3, 3), "gbs_vs_minimum": round(24.0 * pts / dt / 1e9, 1)}
+    finally:
+        os.environ.pop("SCOMP_VARCOEF", None)
+        if saved is not None:
+            os.environ["SCOMP_VARCOEF"] = saved
+    return out
 
 
 def spinodal_bench(native, torch):

@@ -202,9 +202,13 @@ sc_status sc_apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc
  * not overlap them. SC_BC_PERIODIC: indices wrap. SC_BC_HALO: in->halo >=
  * rA + rB and mob->halo >= rB (rA, rB the largest inner and outer radii),
  * since mob * inner(in) is needed on the grid plus the ring the outer
- * stencils read. 1 <= nterms <= 16. Each term is two sweeps through a
- * library workspace, so the call returns after its work on `stream` has
- * completed. Errors: SC_EINVAL, SC_EUNSUPPORTED, SC_ENOMEM, SC_EDEVICE.
+ * stencils read. 1 <= nterms <= 16. On 2D grids with nterms <= 4, inner
+ * stencils of at most 40 and outer ones of at most 16 nonzero taps,
+ * rB <= 2 and rA + rB <= 6, one fused kernel computes the sum and the call
+ * is asynchronous on `stream`. Otherwise each term is two sweeps through a
+ * library workspace, and the call returns after its work on `stream` has
+ * completed. The two forms sum in different orders; results agree to
+ * rounding. Errors: SC_EINVAL, SC_EUNSUPPORTED, SC_ENOMEM, SC_EDEVICE.
  */
 sc_status sc_apply_varcoef(int32_t nterms, const sc_stencil* const* inner, const sc_stencil* const* outer,
                            double h, const sc_grid* mob, const sc_grid* in, sc_grid* out, sc_bc bc,

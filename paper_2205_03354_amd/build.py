@@ -44,7 +44,7 @@ def _units():
     units = []
     for name in ("abi.cpp", "stencil.cpp", "solver.cpp", "server.cpp", "precond.cpp", "imex.cpp"):
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name + ".o"), ["-x", "hip"]))
-    for name in ("launch_host.hip", "elementwise.hip", "csr.hip", "small.hip"):
+    for name in ("launch_host.hip", "elementwise.hip", "csr.hip", "small.hip", "varcoef.hip"):
         units.append((os.path.join(CSRC, name), os.path.join(BUILD, name + ".o"), []))
     for part in range(NPARTS):
         units.append((os.path.join(CSRC, "dispatch.hip"), os.path.join(BUILD, f"dispatch_{part}.o"),

@@ -200,6 +200,30 @@ struct CombineTerms {
 hipError_t launch_combine(const CombineTerms& t, const double* base, double* out, const Layout& lay,
                           const int64_t* n, hipStream_t st);
 
+// Fused 2D variable-coefficient composition (varcoef.hip): a term list
+// whose taps are given as offsets into the kernel's LDS tiles (rows of x
+// kVcPitchX apart, rows of w kVcPitchW apart; w is kVcTileX wide), inner
+// lists padded with zero weights to a multiple of four taps and outer lists
+// to an even count.
+constexpr int kVcTileX = 64;
+constexpr int kVcMaxTerms = 4, kVcMaxTapsA = 40, kVcMaxTapsB = 16;
+constexpr int kVcMaxRing = 6, kVcMaxOuterR = 2;  // RA + RB, RB
+constexpr int kVcPitchX = kVcTileX + 2 * kVcMaxRing, kVcPitchW = kVcTileX;
+template <typename T>
+struct VcTerms {
+  int n = 0, RA = 0, RB = 0;
+  int na[kVcMaxTerms] = {}, nb[kVcMaxTerms] = {};
+  int aoff[kVcMaxTerms][kVcMaxTapsA] = {};
+  int boff[kVcMaxTerms][kVcMaxTapsB] = {};
+  T aw[kVcMaxTerms][kVcMaxTapsA] = {};
+  T bw[kVcMaxTerms][kVcMaxTapsB] = {};
+};
+// y (interior, row pitch py) = sum_t B_t(M * A_t(x)); x and M point at
+// their interiors. periodic: indices wrap; else x carries a ring of RA + RB
+// and M one of RB. terms points at a VcTerms<double> or VcTerms<float>.
+hipError_t launch_varcoef_fused(int dtype, const void* x, int64_t px, const void* m, int64_t pm, void* y, int64_t py,
+                                int64_t n0, int64_t n1, bool periodic, const void* terms, hipStream_t st);
+
 // ------------------------------------------------------ entry-point bodies
 sc_status stencil_create(int32_t dim, int32_t npts, const int32_t* offsets, const int64_t* num,
                          int64_t den, int32_t hpow, sc_stencil** out);

@@ -815,9 +815,70 @@ sc_status apply_composed(const sc_stencil* s, double h, const sc_grid* in, sc_gr
   return launch(L, st);
 }
 
-// y = sum_t B_t(M * A_t(x)): per term, one sweep writes w = M * A_t(x) on
-// the grid plus the ring B_t reads (a library workspace), and one sweep
-// applies B_t to w, writing (first term) or accumulating into y.
+namespace {
+
+// nonzero taps of a stencil, weights num / (den h^p) rounded as the sweeps
+// round them (extended precision, then double, then the grid's dtype)
+template <typename T>
+int vc_taps(const sc_stencil* s, double h, int W, int cap, int pad, int* off, T* w) {
+  long double hp = 1.0L;
+  for (int i = 0; i < std::abs(s->hpow); ++i) hp *= (long double)h;
+  if (s->hpow < 0) hp = 1.0L / hp;
+  int n = 0;
+  for (size_t t = 0; t < s->num.size(); ++t) {
+    if (s->num[t] == 0) continue;
+    if (n == cap) return -1;
+    off[n] = s->off[t][1] * W + s->off[t][0];
+    w[n++] = (T)(double)((long double)s->num[t] / ((long double)s->den * hp));
+  }
+  while (n % pad) {  // pad with zero weights at the point itself
+    off[n] = 0;
+    w[n++] = T(0);
+  }
+  return n;
+}
+
+// The fused kernel takes terms of at most kVcMaxTapsA inner and kVcMaxTapsB
+// outer taps (after padding to multiples of 4 and 2), rA + rB <= kVcMaxRing
+// and rB <= kVcMaxOuterR.
+// SCOMP_VARCOEF=twosweep keeps the two-sweep form (for comparisons).
+bool varcoef_fusable(int nterms, const sc_stencil* const* inner, const sc_stencil* const* outer, int rA, int rB,
+                     const int64_t* n) {
+  if (const char* e = std::getenv("SCOMP_VARCOEF"))
+    if (std::strcmp(e, "twosweep") == 0) return false;
+  if (nterms > kVcMaxTerms || rB > kVcMaxOuterR || rA + rB > kVcMaxRing || (n[1] + 15) / 16 > 65535) return false;
+  auto padded = [](const sc_stencil* s, int64_t pad) {
+    int64_t c = 0;
+    for (int64_t v : s->num) c += v != 0;
+    return (c + pad - 1) / pad * pad;
+  };
+  for (int t = 0; t < nterms; ++t)
+    if (padded(inner[t], 4) > kVcMaxTapsA || padded(outer[t], 2) > kVcMaxTapsB) return false;
+  return true;
+}
+
+template <typename T>
+hipError_t varcoef_fused(int nterms, const sc_stencil* const* inner, const sc_stencil* const* outer, double h, int rA,
+                         int rB, const sc_grid* M, const sc_grid* in, sc_grid* out, bool per, hipStream_t st) {
+  VcTerms<T> tm;
+  tm.n = nterms;
+  tm.RA = rA;
+  tm.RB = rB;
+  for (int t = 0; t < nterms; ++t) {
+    tm.na[t] = vc_taps(inner[t], h, kVcPitchX, kVcMaxTapsA, 4, tm.aoff[t], tm.aw[t]);
+    tm.nb[t] = vc_taps(outer[t], h, kVcPitchW, kVcMaxTapsB, 2, tm.boff[t], tm.bw[t]);
+    if (tm.na[t] < 0 || tm.nb[t] < 0) return hipErrorInvalidValue;
+  }
+  return launch_varcoef_fused(in->dtype, interior(in), in->pitch[0], interior(M), M->pitch[0], interior(out),
+                              out->pitch[0], in->n[0], in->n[1], per, &tm, st);
+}
+
+}  // namespace
+
+// y = sum_t B_t(M * A_t(x)). On 2D grids with few, small terms one fused
+// kernel does it (varcoef.hip). Otherwise, per term, one sweep writes
+// w = M * A_t(x) on the grid plus the ring B_t reads (a library workspace),
+// and one sweep applies B_t to w, writing (first term) or accumulating into y.
 sc_status apply_varcoef(int nterms, const sc_stencil* const* inner, const sc_stencil* const* outer, double h,
                         const sc_grid* M, const sc_grid* in, sc_grid* out, sc_bc bc, hipStream_t st) {
   sc_status r;
@@ -858,6 +919,15 @@ sc_status apply_varcoef(int nterms, const sc_stencil* const* inner, const sc_ste
     return SC_EINVAL;
   }
   const int dim = in->dim;
+  if (dim == 2 && varcoef_fusable(nterms, inner, outer, rA, rB, in->n)) {
+    const hipError_t e = in->dtype == SC_F64 ? varcoef_fused<double>(nterms, inner, outer, h, rA, rB, M, in, out, per, st)
+                                             : varcoef_fused<float>(nterms, inner, outer, h, rA, rB, M, in, out, per, st);
+    if (e != hipSuccess) {
+      set_error("device error: %s", hipGetErrorString(e));
+      return SC_EDEVICE;
+    }
+    return SC_OK;
+  }
   const int wr = per ? 0 : rB;  // ring of the workspace
   int64_t ne[3] = {in->n[0], in->n[1], in->n[2]};
   for (int a = 0; a < dim; ++a) ne[a] += 2 * wr;

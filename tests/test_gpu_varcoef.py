@@ -47,9 +47,20 @@ def _gpu(native, terms, M, x, bc, halo, dtype, mob_halo=0):
     return y.double().cpu().numpy()
 
 
+@pytest.fixture(params=["fused", "twosweep"])
+def form(request, monkeypatch):
+    # 2D calls take the fused kernel unless SCOMP_VARCOEF=twosweep; 3D calls
+    # always take the two-sweep form
+    if request.param == "twosweep":
+        monkeypatch.setenv("SCOMP_VARCOEF", "twosweep")
+    else:
+        monkeypatch.delenv("SCOMP_VARCOEF", raising=False)
+    return request.param
+
+
 @pytest.mark.parametrize("dim,shape", [(2, (77, 301)), (2, (35, 1000)), (3, (20, 17, 33)), (3, (40, 9, 70))])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_unit_mobility_integer_bit_exact(native, dim, shape, dtype):
+def test_unit_mobility_integer_bit_exact(native, form, dim, shape, dtype):
     L = R.laplacian(dim)
     terms = OP.flux_terms(dim, L)
     C = None
@@ -65,8 +76,9 @@ def test_unit_mobility_integer_bit_exact(native, dim, shape, dtype):
 
 
 @pytest.mark.parametrize("dim,shape,fourth", [(2, (77, 301), False), (2, (130, 257), True), (2, (5, 6), False),
+                                              (2, (64, 16), True), (2, (3, 200), True),
                                               (3, (20, 17, 33), False), (3, (6, 5, 7), False)])
-def test_random_mobility_parity(native, dim, shape, fourth):
+def test_random_mobility_parity(native, form, dim, shape, fourth):
     terms = OP.flux_terms(dim, R.laplacian(dim, fourth))
     rA = max(A.radius() for A, _ in terms)
     rB = max(B.radius() for _, B in terms)
@@ -109,6 +121,34 @@ def test_manufactured_order_on_gpu(native):
         hs.append(h)
     rate = math.log(errs[1] / errs[2]) / math.log(hs[1] / hs[2])
     assert abs(rate - 2.0) < 0.1, (errs, rate)
+
+
+def test_fused_and_two_sweep_agree(native, monkeypatch):
+    # the two forms of the same sum agree to rounding on ragged 2D tiles, in
+    # both boundary modes and both dtypes; five terms (beyond the fused
+    # kernel's four) take the two-sweep form and still match the oracle
+    terms = OP.flux_terms(2, R.laplacian(2, True))
+    rA = max(A.radius() for A, _ in terms)
+    rB = max(B.radius() for _, B in terms)
+    shape = (131, 47)
+    x = S.uniform_field(shape, seed=41)
+    M = 1.0 + 0.5 * S.uniform_field(shape, seed=42)
+    xh = S.uniform_field(tuple(s + 2 * (rA + rB) for s in shape), seed=43)
+    Mh = 1.0 + 0.5 * S.uniform_field(tuple(s + 2 * rB for s in shape), seed=44)
+    cases = [(M, x, native.SC_BC_PERIODIC, 0, 0, capi.PERIODIC), (Mh, xh, native.SC_BC_HALO, rA + rB, rB, capi.HALO)]
+    for Mi, xi, bc, halo, mh, mode in cases:
+        sc = _scale(terms, Mi, xi, mode, halo)
+        for dtype, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+            monkeypatch.delenv("SCOMP_VARCOEF", raising=False)
+            a = _gpu(native, terms, Mi, xi, bc, halo, dtype, mob_halo=mh)
+            monkeypatch.setenv("SCOMP_VARCOEF", "twosweep")
+            b = _gpu(native, terms, Mi, xi, bc, halo, dtype, mob_halo=mh)
+            assert np.max(np.abs(a - b)) / sc <= tol
+    monkeypatch.delenv("SCOMP_VARCOEF", raising=False)
+    five = terms + terms[:1] + terms[:1] + terms[1:2]
+    ref = OP.varcoef_apply(five, M, x, capi.PERIODIC)
+    got = _gpu(native, five, M, x, native.SC_BC_PERIODIC, 0, torch.float64)
+    assert np.max(np.abs(got - ref)) / _scale(five, M, x, capi.PERIODIC, 0) <= 1e-12
 
 
 def test_varcoef_errors(native):
