@@ -11,6 +11,10 @@
 
 #include "internal.hpp"
 
+#ifndef VC_WAVES
+#define VC_WAVES 4
+#endif
+
 namespace sc {
 
 namespace {
@@ -27,8 +31,10 @@ constexpr int kXW = kVcPitchX, kXH = kWY + 2 * kMaxRA;
 constexpr int kXRowSlots = (kXH + 3) / 4, kXSideSlots = (2 * kMaxRA * kXH + kNT - 1) / kNT;
 static_assert(kXW >= kWX + 2 * kMaxRA, "x rows hold 64 + 2 RA columns");
 static_assert(kVcPitchW == kWX, "outer tap offsets use the w pitch");
-// lanes past the output columns still read up to 2 RB past a w row
-constexpr int kWPad = 2 * kVcMaxOuterR;
+// Output row slots past the tile's last output row and lanes past its last
+// output column are still summed (and dropped): they read up to 2 RB rows
+// below w and 2 RB columns past a row.
+constexpr int kWPad = 2 * kVcMaxOuterR * kWX + 2 * kVcMaxOuterR;
 
 // floor(i / d) for 0 <= i < 2^16 and 0 < d < 2^8, with mg = floor((2^32 - 1)
 // / d) + 1: the product overshoots i / d by less than i d / 2^32 < 2^-8, which
@@ -81,20 +87,27 @@ __device__ __forceinline__ void fetch(T (&vr)[NR], T (&vs)[NS], const T* __restr
   }
 }
 
-// Tile q of a round of G tiles handled by the block with index b: blocks are
-// dealt to the 8 XCDs in turn, so block b runs on XCD b % 8; that XCD gets
-// the contiguous eighth of the round's tiles, whose shared rings then meet
-// in one L2.
-__device__ __forceinline__ int tile_of(int round, int b, int G) { return round * G + (b % 8) * (G / 8) + b / 8; }
+// The tile a block takes in a given round, or -1 when it has none left.
+// Blocks are dealt to the 8 XCDs in turn, so block b runs on XCD b % 8; the
+// XCD owns the contiguous eighth of all tiles (row-major), which its G / 8
+// blocks take in order, so the rings that vertically adjacent tiles share
+// meet in one L2, a round or two apart.
+__device__ __forceinline__ int tile_of(int round, int b, int G, int ntiles) {
+  const int xcd = b % 8, per = G / 8;
+  const int lo = (int)((int64_t)ntiles * xcd / 8), hi = (int)((int64_t)ntiles * (xcd + 1) / 8);
+  const int q = lo + round * per + b / 8;
+  return q < hi ? q : -1;
+}
 
-// One workgroup walks tiles (tile_of order). Per tile: x with a ring of
+// One workgroup walks its tiles (tile_of). Per tile: x with a ring of
 // RA + RB around the outputs goes to LDS, M stays in the registers of the
 // threads that form w at its points, w = M * A_t(x) goes to LDS, and B_t(w)
 // accumulates in registers; the next tile's x and M are in flight meanwhile.
 // Tap loops are outermost, so a tap's offset and weight serve every row a
 // wave owns, at immediate LDS offsets.
 template <typename T, bool PER>
-__global__ void __launch_bounds__(kNT) varcoef_fused_kernel(const T* __restrict__ x, int64_t px,
+__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(VC_WAVES, VC_WAVES)))
+varcoef_fused_kernel(const T* __restrict__ x, int64_t px,
                                                             const T* __restrict__ m, int64_t pm, T* __restrict__ y,
                                                             int64_t py, int n0, int n1, int tiles_x, int ntiles,
                                                             VcTerms<T> tm) {
@@ -106,9 +119,8 @@ __global__ void __launch_bounds__(kNT) varcoef_fused_kernel(const T* __restrict_
   const unsigned mgx = 0xFFFFFFFFu / (unsigned)(2 * RA) + 1u;
   const int G = (int)gridDim.x, b = (int)blockIdx.x;
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  // a block's positions past ntiles (in the last round only) hold no tile
-  int round = 0, q = tile_of(0, b, G);
-  if (q >= ntiles) return;
+  int round = 0, q = tile_of(0, b, G, ntiles);
+  if (q < 0) return;
   T xr[kXRowSlots], xsd[kXSideSlots], mr[kWSlots], mc[kWSlots], none[1];
   {
     const int X0 = (q % tiles_x) * TX - RB, Y0 = (q / tiles_x) * TY - RB;  // w's corner
@@ -136,12 +148,15 @@ __global__ void __launch_bounds__(kNT) varcoef_fused_kernel(const T* __restrict_
 #pragma unroll
     for (int k = 0; k < kWSlots; ++k) mc[k] = mr[k];
     // the next tile of this block, prefetched across this tile's work
-    const int qn = tile_of(++round, b, G);
-    if (qn < ntiles) {
+    const int qn = tile_of(++round, b, G, ntiles);
+    if (qn >= 0) {
       const int X1 = (qn % tiles_x) * TX - RB, Y1 = (qn / tiles_x) * TY - RB;
       fetch<kXRowSlots, kXSideSlots, PER>(xr, xsd, x, px, X1 - RA, Y1 - RA, RA, XH, mgx, RA + RB, n0, n1);
       fetch<kWSlots, 1, PER>(mr, none, m, pm, X1, Y1, 0, kWY, 1u, RB, n0, n1);
     }
+    // keep the prefetch ahead of this tile's work (the compiler would
+    // otherwise sink the loads to their use, a tile later)
+    asm volatile("" ::: "memory");
     T acc[kWSlots];
 #pragma unroll
     for (int r = 0; r < kWSlots; ++r) acc[r] = T(0);
@@ -152,11 +167,21 @@ __global__ void __launch_bounds__(kNT) varcoef_fused_kernel(const T* __restrict_
 #pragma unroll
       for (int j = 0; j < kWSlots; ++j) s[j] = T(0);
       for (int k = 0; k < na; k += 4) {  // na is a multiple of 4
+        // four taps' reads in flight together (the scheduler would
+        // otherwise funnel them through one register pair)
+        T v[4][kWSlots];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const T w = tm.aw[t][k + u], *p = xrow0 + tm.aoff[t][k + u];
+          const T* p = xrow0 + tm.aoff[t][k + u];
 #pragma unroll
-          for (int j = 0; j < kWSlots; ++j) s[j] = __builtin_fma(w, p[4 * j * kXW], s[j]);
+          for (int j = 0; j < kWSlots; ++j) v[u][j] = p[4 * j * kXW];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const T w = tm.aw[t][k + u];
+#pragma unroll
+          for (int j = 0; j < kWSlots; ++j) s[j] = __builtin_fma(w, v[u][j], s[j]);
         }
       }
 #pragma unroll
@@ -164,12 +189,19 @@ __global__ void __launch_bounds__(kNT) varcoef_fused_kernel(const T* __restrict_
       __syncthreads();
       const int nb = tm.nb[t];
       for (int k = 0; k < nb; k += 2) {  // nb is even
+        T v[2][kWSlots];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const T w = tm.bw[t][k + u], *p = wrow0 + tm.boff[t][k + u];
+          const T* p = wrow0 + tm.boff[t][k + u];
 #pragma unroll
-          for (int r = 0; r < kWSlots; ++r)
-            if (wv + 4 * r < TY) acc[r] = __builtin_fma(w, p[4 * r * kWX], acc[r]);
+          for (int r = 0; r < kWSlots; ++r) v[u][r] = p[4 * r * kWX];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const T w = tm.bw[t][k + u];
+#pragma unroll
+          for (int r = 0; r < kWSlots; ++r) acc[r] = __builtin_fma(w, v[u][r], acc[r]);
         }
       }
     }
@@ -181,7 +213,7 @@ __global__ void __launch_bounds__(kNT) varcoef_fused_kernel(const T* __restrict_
         if (wv + 4 * r < TY && gy < n1) y[(int64_t)gy * py + gx] = acc[r];
       }
     }
-    if (qn >= ntiles) break;
+    if (qn < 0) break;
     q = qn;
   }
 }
