@@ -343,8 +343,11 @@ __global__ void __launch_bounds__(kNT) finish_kernel(FinArgs f) {
   if constexpr (FK == FIN_RESID) {
     s->rr_true = total;
     if (f.flag) {
+      // restart the recurrence from the true residual; flag 2 also sets
+      // its stop to c <b, b> (a restart aims below the tolerance)
       s->rr = total;
       s->beta = 0.0;
+      if (f.flag == 2) s->rr_stop = f.c * s->bb;
       s->done = (total <= s->rr_stop) ? 1 : 0;
     }
   } else if constexpr (FK == FIN_RHS) {
@@ -408,12 +411,12 @@ hipError_t finish(int fk, DevScalars* s, const double* partials, int n, double c
 }  // namespace
 
 hipError_t launch_resid_dd(const double* x, const Layout& lx, const double* b, double* r, const Layout& lr,
-                           const int64_t* n, const TapTable& taps, DevScalars* s, int flag, double* partials,
-                           hipStream_t st) {
+                           const int64_t* n, const TapTable& taps, DevScalars* s, int flag, double c,
+                           double* partials, hipStream_t st) {
   const int nb = elem_blocks(n);
   hipLaunchKernelGGL(resid_dd_kernel, dim3(nb), dim3(kNT), 0, st, x, lx.pitch, lx.zpitch, b, r, lr.pitch, lr.zpitch,
                      n[0], n[1], n[2], taps, s, flag, partials);
-  return finish(FIN_RESID, s, partials, nb, 0.0, flag, 0, st);
+  return finish(FIN_RESID, s, partials, nb, c, flag, 0, st);
 }
 
 hipError_t launch_pc_init(int dtype, void* S, double* lam, int64_t m, double h, hipStream_t st) {

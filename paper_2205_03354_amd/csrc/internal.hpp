@@ -169,10 +169,11 @@ TapTable tap_table(const KStencil& ks);
 // Ring-mode residual r = b - A x with the stencil sum carried in double-double
 // (error-free products and sums), so that the residual is accurate relative
 // to |b - A x| rather than to |A| |x|; then <r, r> -> rr_true (and a CG
-// restart when flag). x has a ring of width >= the taps' radius.
+// restart when flag; flag 2 also sets rr_stop = c <b, b>). x has a ring of
+// width >= the taps' radius.
 hipError_t launch_resid_dd(const double* x, const Layout& lx, const double* b, double* r, const Layout& lr,
-                           const int64_t* n, const TapTable& taps, DevScalars* s, int flag, double* partials,
-                           hipStream_t st);
+                           const int64_t* n, const TapTable& taps, DevScalars* s, int flag, double c,
+                           double* partials, hipStream_t st);
 // x64 += s32->scale * d32
 hipError_t launch_ir_update(double* x64, const Layout& l64, const float* d32, const Layout& l32,
                             const int64_t* n, const DevScalars* s32, hipStream_t st);

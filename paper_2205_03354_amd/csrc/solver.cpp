@@ -368,14 +368,14 @@ sc_status SolveTask::enqueue_read(bool both) {
 // many orders in the interior (weights ~ 1/h^4, the solution O(1)), so an
 // FP64 stencil sum would round the residual at ~1e-10 relative to |b| on
 // 2048^2 grids; the ring-mode residual is summed in double-double instead.
-sc_status SolveTask::enqueue_residual(int flag) {
+sc_status SolveTask::enqueue_residual(int flag, double c) {
   if (!periodic_) {
     SC_HIP_CHECK(launch_resid_dd((const double*)x_.base, x_.lay, (const double*)b_.base, (double*)r64_.base, r64_.lay,
-                                 spec_.n, taps_, d64_, flag, partials_, st_));
+                                 spec_.n, taps_, d64_, flag, c, partials_, st_));
     return SC_OK;
   }
   return sweep(K_RESID, SC_F64, spec_.ksA, x_.base, &x_.lay, nullptr, b_.base, r64_.base, nullptr, x_.lay, flag, 0,
-               0, 0, d64_);
+               0, c, d64_);
 }
 
 // K CG iterations (direction sweep + update each), replayed from a graph
@@ -600,7 +600,7 @@ sc_status SolveTask::advance(bool* done) {
       break;
     }
     case P_CHECK64:
-      if (h64_->rr_true <= h64_->rr_stop) {
+      if (h64_->rr_true <= o.tol * o.tol * h64_->bb) {  // the tolerance itself, not a restart's stop
         finish(SC_OK);
       } else if (h64_->iter >= o.max_iter) {
         set_error("CG did not reach the tolerance in %lld iterations", (long long)o.max_iter);
@@ -621,7 +621,11 @@ sc_status SolveTask::advance(bool* done) {
         if ((s = enqueue_residual(0)) != SC_OK || (s = enqueue_read(false)) != SC_OK) return s;
         phase_ = P_FINAL;
       } else if (h64_->done == 1) {
-        if ((s = enqueue_residual(1)) != SC_OK) return s;
+        // the recurrence met the tolerance: confirm with the true residual,
+        // and should CG go on from it, let that run aim at half the
+        // tolerance (near the rounding floor a run that stops at the
+        // tolerance itself barely moves the true residual)
+        if ((s = enqueue_residual(2, 0.25 * o.tol * o.tol)) != SC_OK) return s;
         if (pc_ && (s = precondition(false, 1)) != SC_OK) return s;
         if ((s = enqueue_read(false)) != SC_OK) return s;
         ++outer_;
@@ -639,7 +643,7 @@ sc_status SolveTask::advance(bool* done) {
       finish(pending_);
       break;
     case P_OUTER:
-      if (h64_->rr_true <= h64_->rr_stop) {
+      if (h64_->rr_true <= o.tol * o.tol * h64_->bb) {
         finish(SC_OK);
       } else if (h32_->iter >= o.max_iter) {
         set_error("refinement did not reach the tolerance in %lld inner iterations", (long long)o.max_iter);

@@ -121,7 +121,7 @@ class SolveTask {
   };
   sc_status make(Vec* v, int dtype);
   sc_status enqueue_block(bool f32);
-  sc_status enqueue_residual(int flag);
+  sc_status enqueue_residual(int flag, double c = 0.0);
   sc_status enqueue_read(bool both);
   sc_status fall_back_to_f64();
   sc_status make_pc(bool f32);
