@@ -545,8 +545,8 @@ def main():
                          "HBM byte counters against a kernel of known traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the multi-GPU (domain-decomposed) path is not part of "
-              "this build; run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU (domain-decomposed) "
+              "path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
