@@ -123,6 +123,40 @@ def test_manufactured_order_on_gpu(native):
     assert abs(rate - 2.0) < 0.1, (errs, rate)
 
 
+def _extreme_terms(case):
+    L4 = R.laplacian(2, True)
+    wide = [(R.compose(R.embed(R.central_first_4th(), a, 2), L4), R.embed(R.central_first_4th(), a, 2))
+            for a in range(2)]
+    onesided = [(R.compose(R.embed(R.central_first(), a, 2), R.laplacian(2)), R.embed(R.forward_first(), a, 2))
+                for a in range(2)]
+    return {"wide": wide, "onesided": onesided, "four": wide + onesided}[case]
+
+
+@pytest.mark.parametrize("case", ["wide", "onesided", "four"])
+@pytest.mark.parametrize("shape", [(131, 47), (7, 9)])
+def test_widest_rings_and_one_sided_terms(native, form, case, shape):
+    # the fused kernel's largest rings (inner radius 4 around an outer radius
+    # 2: x staged with a ring of 6, w's padded rows read), one-sided outer
+    # stencils and four terms, periodic and in halo mode, against the oracle
+    terms = _extreme_terms(case)
+    rA = max(A.radius() for A, _ in terms)
+    rB = max(B.radius() for _, B in terms)
+    x = S.uniform_field(shape, seed=51)
+    M = 1.0 + 0.5 * S.uniform_field(shape, seed=52)
+    ref = OP.varcoef_apply(terms, M, x, capi.PERIODIC)
+    sc = _scale(terms, M, x, capi.PERIODIC, 0)
+    got = _gpu(native, terms, M, x, native.SC_BC_PERIODIC, 0, torch.float64)
+    assert np.max(np.abs(got - ref)) / sc <= 1e-12
+    got32 = _gpu(native, terms, M, x, native.SC_BC_PERIODIC, 0, torch.float32)
+    assert np.max(np.abs(got32 - ref)) / sc <= 1e-5
+    halo = rA + rB
+    xh = S.uniform_field(tuple(s + 2 * halo for s in shape), seed=53)
+    Mh = 1.0 + 0.5 * S.uniform_field(tuple(s + 2 * rB for s in shape), seed=54)
+    ref = OP.varcoef_apply(terms, Mh, xh, capi.HALO, halo)
+    got = _gpu(native, terms, Mh, xh, native.SC_BC_HALO, halo, torch.float64, mob_halo=rB)
+    assert np.max(np.abs(got - ref)) / _scale(terms, Mh, xh, capi.HALO, halo) <= 1e-12
+
+
 def test_fused_and_two_sweep_agree(native, monkeypatch):
     # the two forms of the same sum agree to rounding on ragged 2D tiles, in
     # both boundary modes and both dtypes; five terms (beyond the fused
