@@ -96,8 +96,10 @@ struct Taps {
   T w[N];
 };
 
-// Device scalars of one Krylov solve, written only by the one-block finish
-// kernels (kernels of one solve are serialised on its stream).
+// Device scalars of one Krylov solve, written by the one-block finish
+// kernels and by thread 0 of block 0 of the CG update and of a direction
+// sweep that folds the update's finish in (kernels of one solve are
+// serialised on its stream; no kernel reads a field it writes).
 struct alignas(64) DevScalars {
   double rr;        // <r, r> of the current recurrence residual
   double pq;        // <p, A p>
@@ -111,7 +113,8 @@ struct alignas(64) DevScalars {
   int done;         // 0 running, 1 recurrence converged, 2 breakdown
   int slots;        // partial sums written by the last direction sweep
   double rz;        // preconditioned CG: <r, M^-1 r>
-  double pad[4];
+  double rr_prev;   // the rr the last CG update formed alpha with
+  double pad[3];
 };
 
 // ---------------------------------------------------------------------------
@@ -182,6 +185,75 @@ __device__ __forceinline__ double sum_partials(const double* partials, int n) {
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += NT) s += partials[i];
   return block_sum<NT>(s);
+}
+
+// Threads of the finish kernel (elementwise.hip): its block of partial sums.
+constexpr int kFinNT = 256;
+// Partial slots a folding sweep loads at once (the CG update writes at most
+// this many).
+constexpr int kFoldSlots = 1024;
+
+// The update finish (FIN_UPDATE: iteration count, stop test, beta, rr)
+// folded into the direction sweep that follows the update: every block of
+// NT threads forms the total of the update's <r, r> partials in the finish
+// kernel's order (kFinNT threads striding the slots, each wave's butterfly,
+// the waves added in order), so beta and the stop test are bit for bit the
+// finish kernel's; thread 0 of block 0 records them. Returns false once the
+// recurrence has converged (the sweep then has nothing to do).
+template <int NT>
+__device__ __forceinline__ bool fold_update(DevScalars* s, const double* partials, int n, double* beta) {
+  double t = 0.0;
+  if constexpr (NT == 64) {
+    // lane l plays finish thread w 64 + l for each wave w; the first
+    // kFoldSlots slots are loaded in one go (one memory latency), any
+    // further ones after them, in the same per-thread order
+    constexpr int W = kFinNT / 64;
+    double v[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) v[w] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kFoldSlots / kFinNT; ++k) {
+      double x[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int i = k * kFinNT + w * 64 + (int)threadIdx.x;
+        x[w] = i < n ? partials[i] : 0.0;
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        if (k * kFinNT + w * 64 + (int)threadIdx.x < n) v[w] += x[w];
+    }
+    for (int base = kFoldSlots; base < n; base += kFinNT) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int i = base + w * 64 + (int)threadIdx.x;
+        if (i < n) v[w] += partials[i];
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v[w] += __shfl_xor(v[w], off, 64);
+      t += v[w];
+    }
+  } else {
+    static_assert(NT == kFinNT, "a folding sweep runs 64 or kFinNT threads");
+    __shared__ double tot;
+    const double v = sum_partials<NT>(partials, n);
+    if (threadIdx.x == 0) tot = v;
+    __syncthreads();
+    t = tot;
+  }
+  const double rr_old = s->rr_prev;
+  const bool stop = t <= s->rr_stop;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s->iter += 1;
+    if (stop) s->done = 1;
+    s->beta = t / rr_old;
+    s->rr = t;
+  }
+  *beta = t / rr_old;
+  return !stop;
 }
 
 // What the finish kernel does with the total.

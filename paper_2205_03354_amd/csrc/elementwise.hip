@@ -11,6 +11,7 @@ namespace sc {
 namespace {
 
 constexpr int kNT = 256;
+static_assert(kNT == kFinNT, "the update finish folded into a sweep uses this order");
 
 // Rows [r0, r1) of the interior assigned to this block; row rho is
 // (j, k) = (rho % n1, rho / n1).
@@ -46,6 +47,7 @@ __global__ void __launch_bounds__(kNT)
     s_alpha = ok ? (pc ? s->rz : s->rr) / pq : 0.0;
     if (blockIdx.x == 0) {
       s->pq = pq;
+      s->rr_prev = s->rr;
       if (ok)
         s->alpha = s_alpha;
       else
@@ -236,6 +238,7 @@ int elem_blocks(const int64_t* n) {
   return (int)(rows < kElemBlocks ? rows : kElemBlocks);
 }
 
+
 // t /= (lx_i + ly_j + lz_k)^2 : the squared Dirichlet Laplacian in its
 // sine eigenbasis (lz = 0 in 2D)
 template <typename T>
@@ -379,6 +382,8 @@ __global__ void __launch_bounds__(kNT) finish_kernel(FinArgs f) {
 
 }  // namespace
 
+int update_slots(const int64_t* n) { return elem_blocks(n); }
+
 hipError_t launch_finish(int fk, const FinArgs& f, hipStream_t st) {
   switch (fk) {
     case FIN_RESID: hipLaunchKernelGGL(finish_kernel<FIN_RESID>, dim3(1), dim3(kNT), 0, st, f); break;
@@ -456,7 +461,7 @@ hipError_t launch_pc_dot(int dtype, const void* r, const void* z, const Layout& 
 
 hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
                             const Layout& lay, const int64_t* n, DevScalars* s, const double* pq_partials,
-                            int pc, double* partials, hipStream_t st) {
+                            int pc, double* partials, bool fin, hipStream_t st) {
   const int nb = elem_blocks(n);
   if (dtype == SC_F64) {
     hipLaunchKernelGGL(cg_update_kernel<double>, dim3(nb), dim3(kNT), 0, st, (double*)x, (double*)r,
@@ -467,6 +472,7 @@ hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const vo
                        (const float*)p, (const float*)q, lay.pitch, lay.zpitch, n[0], n[1], n[2], s,
                        pq_partials, pc, partials);
   }
+  if (!fin) return hipGetLastError();
   return finish(FIN_UPDATE, s, partials, nb, 0.0, 0, 1, st);
 }
 

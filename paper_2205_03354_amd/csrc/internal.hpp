@@ -91,6 +91,8 @@ struct SweepLaunch {
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
   double c3 = 1.0;  // K_CHRHS: weight of the centre value
   int flag = 0;
+  const double* fold = nullptr;  // K_CGDIR: finish the CG update here from these partials
+  int fold_n = 0;
   bool vec_store = false;
   bool in_aligned = false;  // in / in2 / aux rows start on 16-byte boundaries
   // Ring mode: columns [in_xlo, in_xhi) of every in / in2 row and [0, aux_xhi)
@@ -132,18 +134,21 @@ struct Layout {
 };
 
 constexpr int kElemBlocks = 1024;  // blocks of the element-wise kernels
+static_assert(kElemBlocks <= kFoldSlots, "a folding sweep loads the update's partials at once");
 
 // The one-block second half of a grid reduction (see FinKind): sums the
 // partials of the kernel launched just before on `st` and finalises.
 hipError_t launch_finish(int fk, const FinArgs& f, hipStream_t st);
 
-// x += alpha p; r -= alpha q; <r, r> -> beta and the stop test, with
-// alpha = (pc ? rz : rr) / <p, q> formed by every block from the s->slots
-// partials of the direction sweep just before (pq_partials must differ from
-// partials).
+// x += alpha p; r -= alpha q; <r, r> partials, with alpha = (pc ? rz : rr)
+// / <p, q> formed by every block from the s->slots partials of the direction
+// sweep just before (pq_partials must differ from partials). fin: the
+// finish kernel turns the partials into beta and the stop test; otherwise
+// the next direction sweep folds that in (update_slots(n) partials).
 hipError_t launch_cg_update(int dtype, void* x, void* r, const void* p, const void* q,
                             const Layout& lay, const int64_t* n, DevScalars* s, const double* pq_partials,
-                            int pc, double* partials, hipStream_t st);
+                            int pc, double* partials, bool fin, hipStream_t st);
+int update_slots(const int64_t* n);
 // r32 = r64 / s; d32 = 0; rr = <r32, r32>, rr_stop = inner_tol^2 rr. A
 // restart (keep_direction 0) sets s = sqrt(s64->rr_true) and beta = 0; a
 // reliable update (keep_direction 1) keeps s and rescales beta so that the

@@ -57,6 +57,8 @@ SweepArgs<T> make_args(const SweepLaunch& L) {
   a.partials = L.partials;
   a.c0 = L.c0; a.c1 = L.c1; a.c2 = L.c2; a.c3 = L.c3;
   a.flag = L.flag;
+  a.fold = L.fold;
+  a.fold_n = L.fold_n;
   a.vec_store = L.vec_store ? 1 : 0;
   a.in_aligned = L.in_aligned ? 1 : 0;
   a.alt = 0;

@@ -64,6 +64,8 @@ struct SweepArgs {
   double c0, c1, c2;      // K_CHRHS: dt, 1+S; K_BVPRHS/K_CHRHS: c2 = tol^2
   double c3;              // K_CHRHS: weight of the centre value u
   int flag;               // K_RESID: 1 = also (re)start the CG recurrence
+  const double* fold;     // K_CGDIR: the CG update's <r, r> partials to finish here (or null)
+  int fold_n;             // their count
 };
 
 template <typename T, int VEC>
@@ -157,7 +159,18 @@ __global__ void __launch_bounds__(64)
   if constexpr (KIND == K_CGDIR) {
     if (a.scal->done) return;
   }
-  const T beta = (KIND == K_CGDIR) ? (T)a.scal->beta : T(0);
+  // beta from the finish kernel, or formed here from the CG update's
+  // partials (fold_update); a converged recurrence leaves nothing to do
+  T beta = T(0);
+  if constexpr (KIND == K_CGDIR) {
+    if (a.fold) {
+      double b = 0.0;
+      if (!fold_update<64>(a.scal, a.fold, a.fold_n, &b)) return;
+      beta = (T)b;
+    } else {
+      beta = (T)a.scal->beta;
+    }
+  }
   const T c1 = (T)a.c1;
 
   const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);

@@ -63,7 +63,18 @@ __global__ void __launch_bounds__(64)
   if constexpr (KIND == K_CGDIR) {
     if (a.scal->done) return;
   }
-  const T beta = (KIND == K_CGDIR) ? (T)a.scal->beta : T(0);
+  // beta from the finish kernel, or formed here from the CG update's
+  // partials (fold_update); a converged recurrence leaves nothing to do
+  T beta = T(0);
+  if constexpr (KIND == K_CGDIR) {
+    if (a.fold) {
+      double b = 0.0;
+      if (!fold_update<64>(a.scal, a.fold, a.fold_n, &b)) return;
+      beta = (T)b;
+    } else {
+      beta = (T)a.scal->beta;
+    }
+  }
   const T c1 = (T)a.c1;
 
   // tile order: x fastest, then y, then z chunks

@@ -129,7 +129,8 @@ class SolveTask {
   void finish(sc_status s);
   sc_status sweep(int kind, int dtype, const KStencil& ks, const void* in, const Layout* lin, const void* in2,
                   const void* aux, void* out, void* out2, const Layout& lout, int flag, double c0, double c1,
-                  double c2, DevScalars* sc, const GridView* in_view = nullptr, const GridView* aux_view = nullptr);
+                  double c2, DevScalars* sc, const GridView* in_view = nullptr, const GridView* aux_view = nullptr,
+                  const double* fold = nullptr);
 
   TaskSpec spec_;
   bool periodic_ = false;
