@@ -287,3 +287,42 @@ def test_large_bvps_reach_tolerance_through_restarts(native, N):
     assert st.status == native.SC_OK and st.rel_residual <= 1e-10, st
     rel = OP.bvp_relres_extended(R.biharmonic(2), x, bvp.f, bvp.g, bvp.halo, bvp.h)
     assert rel <= 1e-10, rel
+
+
+def _mixed_spd_3d():
+    # -L + d_x d_y in 3D: symmetric (w(-u) = w(u)) but not mirror-symmetric,
+    # so its direction sweep is the general 3D kernel; SPD since
+    # |sin tx sin ty| <= 2 (sin^2(tx/2) + sin^2(ty/2))
+    dxdy = R.compose(R.embed(R.central_first(), 0, 3), R.embed(R.central_first(), 1, 3))
+    return R.lincomb([(-1, 0, R.laplacian(3)), (1, 0, dxdy)])
+
+
+@pytest.mark.parametrize("case", ["bvp2d", "ch3d", "mixed3d"])
+def test_folded_update_finish_is_bit_identical(native, case):
+    # Within a graph block the CG update's finish (beta, stop test) is formed
+    # by the next direction sweep in the finish kernel's own summation
+    # order; with one iteration per block nothing is folded. Both must give
+    # the same solution bit for bit and the same iteration count.
+    from paper_2205_03354_amd import stencils
+
+    def run(every):
+        if case == "ch3d":
+            u0 = S.zero_mean_uniform((24, 24, 24), seed=61)
+            u = torch.from_numpy(u0).to(DEV)
+            h = 1.0 / 24
+            st = native.ch_step(stencils.laplacian(3), u, h, 4 * h, 0.1 * h * h, 2.0, tol=1e-10, check_every=every)
+            return u.cpu().numpy(), st
+        if case == "bvp2d":
+            op, shape, h = stencils.biharmonic(2), (127, 127), 1.0 / 128
+        else:
+            op, shape, h = lib_stencil(native, _mixed_spd_3d()), (20, 21, 22), 1.0 / 23
+        f = torch.from_numpy(S.uniform_field(shape, seed=62)).to(DEV)
+        u = torch.zeros_like(f)
+        st = native.solve_biharmonic(op, h, f, u, tol=1e-10, check_every=every, onchip=False)
+        return u.cpu().numpy(), st
+
+    x1, s1 = run(1)
+    x2, s2 = run(16)
+    assert s1.rel_residual <= 1e-10 and s2.rel_residual <= 1e-10
+    assert s1.iterations == s2.iterations, (s1, s2)
+    assert np.array_equal(x1, x2)
