@@ -186,38 +186,30 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
   long long it = 0;
   int outer = 1, status = SC_OK;
   bool converged = rr_true <= rr_stop;
+  // CG in its single-reduction form (Chronopoulos and Gear): each iteration
+  // applies A to r (w = A r) and reduces <r, r> and <r, w> together; A p is
+  // carried by the recurrence q = w + beta q. The same iterates as the
+  // textbook form in exact arithmetic, with two barriers per iteration
+  // instead of three. A true-residual restart starts p = r, q = w afresh.
+  double w[kSeg];
+  bool fresh = true;
+  double gamma_old = rr, alpha = 0.0;
   while (!converged) {
-    if (it >= max_iter) {
-      status = SC_ENOTCONV;
-      break;
-    }
-    apply(p, q);
-    double pq = 0.0;
-#pragma unroll
-    for (int j = 0; j < kSeg; ++j) pq += p[j] * q[j];
-    pq = reduce1(pq);
-    if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
-      status = SC_EBREAKDOWN;
-      break;
-    }
-    const double alpha = rr / pq;
-    double rn = 0.0;
+    apply(r, w);
+    double g = 0.0, dl = 0.0;
 #pragma unroll
     for (int j = 0; j < kSeg; ++j) {
-      x[j] = __builtin_fma(alpha, p[j], x[j]);
-      r[j] = __builtin_fma(-alpha, q[j], r[j]);
-      rn += r[j] * r[j];
+      g += r[j] * r[j];
+      dl += r[j] * w[j];
     }
-    rn = reduce1(rn);
-    ++it;
-    if (rn <= rr_stop) {
+    reduce2(g, dl);
+    if (g <= rr_stop && !fresh) {
       // confirm on the true residual; restart the recurrence from it if not
       apply(x, q);
       double rt = 0.0;
 #pragma unroll
       for (int j = 0; j < kSeg; ++j) {
         r[j] = b[j] - q[j];
-        p[j] = r[j];
         rt += r[j] * r[j];
       }
       rt = reduce1(rt);
@@ -229,13 +221,31 @@ __global__ void __launch_bounds__(kNT) small_cg_kernel(const SmallDesc* __restri
         status = SC_ENOTCONV;
         break;
       }
-      rr = rt;
+      fresh = true;
       continue;
     }
-    const double beta = rn / rr;
+    if (it >= max_iter) {
+      status = SC_ENOTCONV;
+      break;
+    }
+    // beta = <r, r> / <r_old, r_old>; <p, A p> = <r, w> - beta <r, r> / alpha_old
+    const double beta = fresh ? 0.0 : g / gamma_old;
+    const double pq = fresh ? dl : dl - beta * g / alpha;
+    if (!(pq > 0.0) || !__builtin_isfinite(pq)) {
+      status = SC_EBREAKDOWN;
+      break;
+    }
+    alpha = g / pq;
 #pragma unroll
-    for (int j = 0; j < kSeg; ++j) p[j] = __builtin_fma(beta, p[j], r[j]);
-    rr = rn;
+    for (int j = 0; j < kSeg; ++j) {
+      p[j] = fresh ? r[j] : __builtin_fma(beta, p[j], r[j]);
+      q[j] = fresh ? w[j] : __builtin_fma(beta, q[j], w[j]);
+      x[j] = __builtin_fma(alpha, p[j], x[j]);
+      r[j] = __builtin_fma(-alpha, q[j], r[j]);
+    }
+    gamma_old = g;
+    fresh = false;
+    ++it;
   }
   if (status != SC_OK) {
     // the true residual of the returned iterate
