@@ -19,9 +19,13 @@ inline int tile_rows_2d(int64_t n1, int64_t strips, int R, int64_t capacity) {
     if (v > 0) return v;
   }
   // as many tiles as the device holds waves of the kernel at once (one
-  // round of waves), but tiles of at least max(4R, 12) rows
+  // round of waves), but tiles of at least max(4R, 12) rows (fewer halo
+  // re-reads), unless tiles that tall would leave over half of those waves
+  // idle: then max(2R, 4) rows (CH steps at 512^2 and 1024^2 21% and 10%
+  // faster, 2048^2 unchanged)
   int64_t ty = (n1 * strips + capacity - 1) / capacity;
-  const int64_t lo = 4 * R > 12 ? 4 * R : 12;
+  int64_t lo = 4 * R > 12 ? 4 * R : 12;
+  if (n1 * strips / lo < capacity / 2) lo = 2 * R > 4 ? 2 * R : 4;
   if (ty < lo) ty = lo;
   if (ty > n1) ty = n1;
   if (ty < 1) ty = 1;
