@@ -385,7 +385,8 @@ def varcoef_bench(native, torch, reps: int = 20):
     mobility (sc_apply_varcoef), in both forms: the fused 2D kernel (x and M
     staged once per tile, w = M * A_t(x) kept in LDS) and the two-sweep form
     (per term, an inner sweep scaled by M into a workspace and an outer
-    sweep)."""
+    sweep); and the 3D form (two sweeps per term) on 256^3 with three
+    terms."""
     import synthetic as S
     from paper_2205_03354_amd import stencils
 
@@ -418,6 +419,23 @@ def varcoef_bench(native, torch, reps: int = 20):
         os.environ.pop("SCOMP_VARCOEF", None)
         if saved is not None:
             os.environ["SCOMP_VARCOEF"] = saved
+    # 3D (two-sweep form): div(M grad(Lap x)) on 256^3, three terms
+    n3 = 256
+    terms3 = stencils.flux_terms(3, stencils.laplacian(3))
+    x3 = torch.from_numpy(S.uniform_field((n3, n3, n3), seed=2)).to(dev)
+    M3 = 1.0 + 0.5 * torch.from_numpy(S.uniform_field((n3, n3, n3), seed=3)).to(dev)
+    y3 = torch.empty_like(x3)
+    for _ in range(2):
+        native.apply_varcoef(terms3, M3, x3, y3, native.SC_BC_PERIODIC, h=1.0 / n3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps // 2):
+        native.apply_varcoef(terms3, M3, x3, y3, native.SC_BC_PERIODIC, h=1.0 / n3)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / (reps // 2)
+    out["3d_256cube_twosweep"] = {"ms_per_apply": round(dt * 1e3, 3),
+                                  "gbs_vs_minimum": round(24.0 * n3 ** 3 / dt / 1e9, 1),
+                                  "terms": 3, "words_per_point_moved": 16}
     return out
 
 
