@@ -197,3 +197,29 @@ def test_varcoef_errors(native):
         native.apply_varcoef([], M, y, y, native.SC_BC_PERIODIC)
     with pytest.raises(native.ScError):  # out aliases in
         native.apply_varcoef(lt, M, y, y, native.SC_BC_PERIODIC)
+
+
+def test_full_size_sampled_parity(native, form):
+    # the benchmark's configuration (4097^2 FP64 periodic, two terms), checked
+    # at sampled outputs: each by the oracle on the periodic patch around it
+    # (halo mode on the wrapped neighbourhood), corners and edges included
+    n = 4097
+    terms = OP.flux_terms(2, R.laplacian(2))
+    rA = max(A.radius() for A, _ in terms)
+    rB = max(B.radius() for _, B in terms)
+    H = rA + rB
+    x = S.uniform_field((n, n), seed=71)
+    M = 1.0 + 0.5 * S.uniform_field((n, n), seed=72)
+    got = _gpu(native, terms, M, x, native.SC_BC_PERIODIC, 0, torch.float64)
+    g = np.random.default_rng(73)
+    pts = [(0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1), (0, n // 2), (n // 2, 0), (61, 17), (62, 18)]
+    pts += [tuple(int(v) for v in g.integers(0, n, 2)) for _ in range(56)]
+    for i, j in pts:
+        rows = np.arange(i - H, i + H + 1) % n
+        cols = np.arange(j - H, j + H + 1) % n
+        xp = x[np.ix_(rows, cols)]
+        Mp = M[np.ix_(rows[rA:-rA], cols[rA:-rA])]
+        ref = OP.varcoef_apply(terms, Mp, xp, capi.HALO, H)
+        sc = float(OP.varcoef_apply([(abs_stencil(A), abs_stencil(B)) for A, B in terms], np.abs(Mp), np.abs(xp),
+                                    capi.HALO, H)[0, 0])
+        assert abs(got[i, j] - ref[0, 0]) <= 1e-12 * sc, (i, j, got[i, j], ref[0, 0])
