@@ -196,6 +196,25 @@ def test_ch_mass_energy_gpu(native, prec):
     assert E_prev < E0
 
 
+@pytest.mark.parametrize("dim,N", [(2, 1024), (3, 256)])
+@pytest.mark.parametrize("prec", ["f64", "f32ir", "f32ru"])
+def test_ch_step_full_size(native, dim, N, prec):
+    # the benchmark's CH configurations at their full sizes, one step in each
+    # precision: the oracle's own apply confirms the step's true relative
+    # residual on the whole grid; mass is conserved and the free energy does
+    # not increase
+    h = 1.0 / N
+    eps, dt, Sst = 4 * h, 0.1 * h * h, 2.0
+    u0 = S.zero_mean_uniform((N,) * dim, seed=5)
+    ug, st = _ch_gpu(native, u0, h, eps, dt, Sst, 1, _PREC[prec](native))
+    A = OP.ch_operator(dim, h, eps, dt, Sst)
+    rel = OP.true_relres(A, ug, OP.ch_rhs(u0, h, dt, Sst), capi.PERIODIC, 1.0)
+    assert rel <= 1e-10 and st[0].rel_residual <= 1e-10, (rel, st[0])
+    assert abs(OP.mass(ug, h) - OP.mass(u0, h)) <= 1e-12
+    E0, E1 = OP.ch_energy(u0, h, eps), OP.ch_energy(ug, h, eps)
+    assert E1 <= E0 + 1e-14 * abs(E0)
+
+
 # --------------------------------------------------------------- preconditioned
 @pytest.mark.parametrize("N", [17, 33, 65, 129])
 @pytest.mark.parametrize("prec", ["f64", "f32ir", "f32ru"])
