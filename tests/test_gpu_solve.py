@@ -293,6 +293,20 @@ def test_large_bvp_reaches_tolerance_with_compensated_residual(native):
     assert rel <= 1e-10, rel
 
 
+@pytest.mark.parametrize("n", [63, 127, 255])
+def test_bvp3d_full_sizes(native, n):
+    # the 3D BVP configuration's sizes (64^3 - 256^3 grids, 25-point L o L,
+    # 2-ring halo from the exact u), preconditioned FP64 CG: the oracle
+    # recomputes the residual with extended-precision sums, and the error
+    # against the manufactured solution is second order (0.79 h^2 at n = 63
+    # from the pinned rates, bounded here by h^2)
+    bvp, x, st = _gpu_bvp(native, 3, n, native.SC_PREC_F64, precond=native.SC_PC_FASTPOISSON)
+    assert st.status == native.SC_OK and st.rel_residual <= 1e-10, st
+    rel = OP.bvp_relres_extended(R.biharmonic(3), x, bvp.f, bvp.g, bvp.halo, bvp.h)
+    assert rel <= 1e-10, rel
+    assert np.max(np.abs(x - bvp.u)) <= bvp.h ** 2
+
+
 @pytest.mark.parametrize("N", [1922, 1968, 2036])
 def test_large_bvps_reach_tolerance_through_restarts(native, N):
     # Near 2000 nodes a side, |b| of these BVPs comes from the ring terms and
