@@ -294,6 +294,81 @@ __global__ void __launch_bounds__(kNT) pc_init_kernel(T* __restrict__ S, double*
   }
 }
 
+// The sine transform of length m split by its symmetry S(k, m-1-j) =
+// (-1)^k S(k, j) (0-based; S(k, j) = sqrt(2/(m+1)) sin(pi (k+1)(j+1)/(m+1))):
+// with u+_j = v_j + v_{m-1-j} (and the middle value when m is odd) in the
+// first hp = ceil(m/2) entries and u-_j = v_j - v_{m-1-j} stored reversed in
+// the last hm = floor(m/2), the transform's even rows are Fo u+ and its odd
+// rows FeR u-. F holds Fo (hp x hp, Fo[a][b] = S(2a, b)) then FeR (hm x hm,
+// FeR[a][c] = S(2a+1, hm-1-c)), column-major. lam lists the 1D eigenvalues
+// in the order the transformed data takes: even k, then odd k.
+template <typename T>
+__global__ void __launch_bounds__(kNT) pc_init_split_kernel(T* __restrict__ F, double* __restrict__ lam, int64_t m,
+                                                            double h) {
+  const int64_t tid = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kNT;
+  const double c0 = sqrt(2.0 / (double)(m + 1));
+  const int64_t period = 2 * (m + 1);
+  const int64_t hp = (m + 1) / 2, hm = m / 2;
+  if (F) {
+    for (int64_t e = tid; e < hp * hp; e += stride) {
+      const int64_t b = e / hp, a = e - b * hp;
+      const int64_t t = ((2 * a + 1) * (b + 1)) % period;
+      F[e] = (T)(c0 * sin(M_PI * (double)t / (double)(m + 1)));
+    }
+    for (int64_t e = tid; e < hm * hm; e += stride) {
+      const int64_t c = e / hm, a = e - c * hm;
+      const int64_t t = ((2 * a + 2) * (hm - c)) % period;
+      F[hp * hp + e] = (T)(c0 * sin(M_PI * (double)t / (double)(m + 1)));
+    }
+  }
+  for (int64_t i = tid; i < m; i += stride) {
+    const int64_t k = i < hp ? 2 * i : 2 * (i - hp) + 1;
+    const double sk = sin(M_PI * (double)(k + 1) / (double)period);
+    lam[i] = -4.0 / (h * h) * sk * sk;
+  }
+}
+
+// (v_j, v_{n-1-j}) -> (v_j + v_{n-1-j}, v_j - v_{n-1-j}) along one axis for
+// j < floor(n/2), at every position of the other two; the middle value (n
+// odd) is copied. The same step folds data before the split transform and
+// unfolds it after the transposed one. in may equal out (each pair is read
+// and written by one thread).
+template <typename T>
+__global__ void __launch_bounds__(kNT)
+    butterfly_kernel(const T* in, T* out, int64_t p, int64_t zp, int64_t n0, int64_t n1, int64_t n2, int axis) {
+  const int64_t n = axis == 0 ? n0 : (axis == 1 ? n1 : n2);
+  const int64_t s = axis == 0 ? 1 : (axis == 1 ? p : zp);
+  const int64_t hm = n / 2, hp = (n + 1) / 2;
+  // the other two extents and strides; the first is the unit-stride one
+  // unless the axis itself is x (then pairs along x are the fastest index)
+  const int64_t oa = axis == 0 ? n1 : n0, ob = axis == 2 ? n1 : n2;
+  const int64_t sa = axis == 0 ? p : 1, sb = axis == 2 ? p : zp;
+  const int64_t total = hp * oa * ob;
+  for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < total; e += (int64_t)gridDim.x * kNT) {
+    int64_t j, ia, ib;
+    if (axis == 0) {
+      j = e % hp;
+      const int64_t r = e / hp;
+      ia = r % oa;
+      ib = r / oa;
+    } else {
+      ia = e % oa;
+      const int64_t r = e / oa;
+      j = r % hp;
+      ib = r / hp;
+    }
+    const int64_t base = ia * sa + ib * sb;
+    if (j < hm) {
+      const T x = in[base + j * s], y = in[base + (n - 1 - j) * s];
+      out[base + j * s] = x + y;
+      out[base + (n - 1 - j) * s] = x - y;
+    } else {
+      out[base + j * s] = in[base + j * s];
+    }
+  }
+}
+
 // Error-free transformations: a + b = s + e exactly (Knuth), a * b = p + e
 // exactly (one FMA).
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
@@ -422,6 +497,33 @@ hipError_t launch_resid_dd(const double* x, const Layout& lx, const double* b, d
   hipLaunchKernelGGL(resid_dd_kernel, dim3(nb), dim3(kNT), 0, st, x, lx.pitch, lx.zpitch, b, r, lr.pitch, lr.zpitch,
                      n[0], n[1], n[2], taps, s, flag, partials);
   return finish(FIN_RESID, s, partials, nb, c, flag, 0, st);
+}
+
+hipError_t launch_pc_init_split(int dtype, void* F, double* lam, int64_t m, double h, hipStream_t st) {
+  int64_t nb = (m * m / 2 + kNT - 1) / kNT;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  if (dtype == SC_F64)
+    hipLaunchKernelGGL(pc_init_split_kernel<double>, dim3((unsigned)nb), dim3(kNT), 0, st, (double*)F, lam, m, h);
+  else
+    hipLaunchKernelGGL(pc_init_split_kernel<float>, dim3((unsigned)nb), dim3(kNT), 0, st, (float*)F, lam, m, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_butterfly(int dtype, const void* in, void* out, const Layout& lay, const int64_t* n, int axis,
+                            hipStream_t st) {
+  const int64_t na = n[axis];
+  const int64_t total = (na + 1) / 2 * (n[0] * n[1] * n[2] / na);
+  int64_t nb = (total + kNT - 1) / kNT;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) nb = 1;
+  if (dtype == SC_F64)
+    hipLaunchKernelGGL(butterfly_kernel<double>, dim3((unsigned)nb), dim3(kNT), 0, st, (const double*)in,
+                       (double*)out, lay.pitch, lay.zpitch, n[0], n[1], n[2], axis);
+  else
+    hipLaunchKernelGGL(butterfly_kernel<float>, dim3((unsigned)nb), dim3(kNT), 0, st, (const float*)in, (float*)out,
+                       lay.pitch, lay.zpitch, n[0], n[1], n[2], axis);
+  return hipGetLastError();
 }
 
 hipError_t launch_pc_init(int dtype, void* S, double* lam, int64_t m, double h, hipStream_t st) {

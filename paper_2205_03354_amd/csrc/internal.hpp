@@ -160,6 +160,13 @@ hipError_t launch_ir_prepare(const double* r64, const Layout& l64, float* r32, f
 // Preconditioner pieces: t /= (lx_i + ly_j + lz_k)^2 (lz may be null), and
 // rz = <r, z>, beta = rz / rz_old (0 when start), both skipped once done.
 hipError_t launch_pc_init(int dtype, void* S, double* lam, int64_t m, double h, hipStream_t st);
+// The split sine transform of length m (even rows from the folded sums,
+// odd rows from the folded differences; see elementwise.hip): F holds the
+// two half matrices, lam the 1D eigenvalues in the transformed data's order.
+hipError_t launch_pc_init_split(int dtype, void* F, double* lam, int64_t m, double h, hipStream_t st);
+// The fold / unfold step of the split transform along `axis` (in may equal out).
+hipError_t launch_butterfly(int dtype, const void* in, void* out, const Layout& lay, const int64_t* n, int axis,
+                            hipStream_t st);
 hipError_t launch_pc_scale(int dtype, void* t, const Layout& lay, const int64_t* n, const double* lx,
                            const double* ly, const double* lz, const DevScalars* s, hipStream_t st);
 hipError_t launch_pc_dot(int dtype, const void* r, const void* z, const Layout& lay, const int64_t* n,

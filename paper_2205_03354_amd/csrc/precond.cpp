@@ -17,7 +17,9 @@
 #include <rocblas/rocblas.h>
 #include <rocfft/rocfft.h>
 
+#include <algorithm>
 #include <array>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 
@@ -77,20 +79,24 @@ rocblas_handle blas_handle() {
   return h;
 }
 
-// C (m x n, ldc) = A (m x k, lda) * B (k x n, ldb), column-major, batched
-// with strides (a zero stride reuses the matrix).
+// C (m x n, ldc) = op(A) (m x k) * op(B) (k x n), column-major (lda, ldb
+// describe A and B as stored), batched with strides (a zero stride reuses
+// the matrix); ta / tb transpose A / B.
 sc_status gemm(rocblas_handle hb, int dtype, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, int64_t sa,
-               const void* B, int64_t ldb, int64_t sb, void* C, int64_t ldc, int64_t sc_, int64_t batch) {
+               const void* B, int64_t ldb, int64_t sb, void* C, int64_t ldc, int64_t sc_, int64_t batch,
+               bool ta = false, bool tb = false) {
   rocblas_status e;
+  const rocblas_operation oa = ta ? rocblas_operation_transpose : rocblas_operation_none;
+  const rocblas_operation ob = tb ? rocblas_operation_transpose : rocblas_operation_none;
   if (dtype == SC_F64) {
     const double one = 1.0, zero = 0.0;
-    e = rocblas_dgemm_strided_batched(hb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)m,
+    e = rocblas_dgemm_strided_batched(hb, oa, ob, (rocblas_int)m,
                                       (rocblas_int)n, (rocblas_int)k, &one, (const double*)A, (rocblas_int)lda, sa,
                                       (const double*)B, (rocblas_int)ldb, sb, &zero, (double*)C, (rocblas_int)ldc,
                                       sc_, (rocblas_int)batch);
   } else {
     const float one = 1.0f, zero = 0.0f;
-    e = rocblas_sgemm_strided_batched(hb, rocblas_operation_none, rocblas_operation_none, (rocblas_int)m,
+    e = rocblas_sgemm_strided_batched(hb, oa, ob, (rocblas_int)m,
                                       (rocblas_int)n, (rocblas_int)k, &one, (const float*)A, (rocblas_int)lda, sa,
                                       (const float*)B, (rocblas_int)ldb, sb, &zero, (float*)C, (rocblas_int)ldc, sc_,
                                       (rocblas_int)batch);
@@ -116,6 +122,18 @@ bool fft_sides(int dim, const int64_t* n) {
   return true;
 }
 
+// The split GEMM transforms halve the flops but add a butterfly pass and a
+// second, half-size GEMM per axis: they pay on large 2D sides (n ~ 2000:
+// about 0.6 ms of GEMM saved per apply for 0.07 ms of butterflies), not on
+// small grids, where launches dominate (65^2: 1.2 -> 2.0 ms per PCG solve),
+// nor in 3D, where the butterflies move as many bytes as the halved GEMMs
+// save (255^3: 43 -> 47 ms).
+bool split_sides(int dim, const int64_t* n) {
+  if (const char* e = std::getenv("SCOMP_PCSPLIT"))  // A/B switch: 0 keeps the full products
+    if (e[0] == '0') return false;
+  return dim == 2 && !fft_sides(dim, n) && std::min(n[0], n[1]) >= kSplitMinSide;
+}
+
 }  // namespace
 
 size_t fastpoisson_bytes(int dim, const int64_t* n, int dtype) {
@@ -133,7 +151,9 @@ size_t fastpoisson_bytes(int dim, const int64_t* n, int dtype) {
   for (int a = 0; a < dim; ++a) {
     bool dup = false;
     for (int c = 0; c < a; ++c) dup = dup || n[c] == n[a];
-    if (!dup) b += (((size_t)(n[a] * n[a]) * es + 4095) & ~(size_t)4095);
+    const size_t hp = (size_t)(n[a] + 1) / 2, hm = (size_t)n[a] / 2;  // the split transform's halves
+    const size_t mat = split_sides(dim, n) ? hp * hp + hm * hm : (size_t)(n[a] * n[a]);
+    if (!dup) b += ((mat * es + 4095) & ~(size_t)4095);
     b += (((size_t)n[a] * 8 + 4095) & ~(size_t)4095);
   }
   return b;
@@ -281,13 +301,16 @@ sc_status FastPoisson::init(int dim, const int64_t* n, double h, int dtype, hipS
     }
     return SC_OK;
   }
+  split_ = split_sides(dim, n_);
   for (int a = 0; a < dim; ++a) {
     int same = -1;
     for (int c = 0; c < a; ++c)
       if (n_[c] == n_[a]) same = c;
     const int64_t m = n_[a];
     void* l = pool_alloc((size_t)m * 8);
-    void* d = same >= 0 ? S_[same] : pool_alloc((size_t)(m * m) * es);
+    const int64_t hp = (m + 1) / 2, hm = m / 2;
+    const int64_t mat = split_ ? hp * hp + hm * hm : m * m;
+    void* d = same >= 0 ? S_[same] : pool_alloc((size_t)mat * es);
     if (!l || !d) {
       if (l) pool_free(l);
       set_error("preconditioner allocation failed");
@@ -298,7 +321,10 @@ sc_status FastPoisson::init(int dim, const int64_t* n, double h, int dtype, hipS
     S_[a] = d;
     lam_[a] = static_cast<double*>(l);
     // the transform and the 1D eigenvalues are generated on the device
-    SC_HIP_CHECK(launch_pc_init(dtype, same >= 0 ? nullptr : d, lam_[a], m, h, st));
+    if (split_)
+      SC_HIP_CHECK(launch_pc_init_split(dtype, same >= 0 ? nullptr : d, lam_[a], m, h, st));
+    else
+      SC_HIP_CHECK(launch_pc_init(dtype, same >= 0 ? nullptr : d, lam_[a], m, h, st));
   }
   if (!blas_handle()) {
     set_error("rocBLAS handle creation failed");
@@ -327,28 +353,91 @@ sc_status FastPoisson::apply(const void* r, void* z, void* tmp, const Layout& la
     if ((e = dst_rows(dx_, tmp, p, tr_, n1, st)) != SC_OK) return e;
     return dst_rows(dy_, tr_, n1, z, p, st);
   }
-  // one sine transform along every axis, in -> out (in and out distinct)
-  auto transform = [&](const void* in, void* out, void* mid) -> sc_status {
-    sc_status r2;
+  if (!split_) {
+    // one sine transform along every axis, in -> out (in and out distinct)
+    auto transform = [&](const void* in, void* out, void* mid) -> sc_status {
+      sc_status r2;
+      if (dim_ == 2) {
+        if ((r2 = gemm(hb, dtype_, n0, n1, n0, S_[0], n0, 0, in, p, 0, mid, p, 0, 1)) != SC_OK) return r2;
+        return gemm(hb, dtype_, n0, n1, n1, mid, p, 0, S_[1], n1, 0, out, p, 0, 1);
+      }
+      // per plane: x (left) then y (right); then z across planes, per row
+      if ((r2 = gemm(hb, dtype_, n0, n1, n0, S_[0], n0, 0, in, p, zp, mid, p, zp, n2)) != SC_OK) return r2;
+      if ((r2 = gemm(hb, dtype_, n0, n1, n1, mid, p, zp, S_[1], n1, 0, out, p, zp, n2)) != SC_OK) return r2;
+      if ((r2 = gemm(hb, dtype_, n0, n2, n2, out, zp, p, S_[2], n2, 0, mid, zp, p, n1)) != SC_OK) return r2;
+      return SC_OK;
+    };
     if (dim_ == 2) {
-      if ((r2 = gemm(hb, dtype_, n0, n1, n0, S_[0], n0, 0, in, p, 0, mid, p, 0, 1)) != SC_OK) return r2;
-      return gemm(hb, dtype_, n0, n1, n1, mid, p, 0, S_[1], n1, 0, out, p, 0, 1);
+      if ((e = transform(r, z, tmp)) != SC_OK) return e;  // S r in z (via tmp)
+      SC_HIP_CHECK(launch_pc_scale(dtype_, z, lay, n_, lam_[0], lam_[1], nullptr, s, st));
+      return transform(z, z, tmp);  // S (...) back into z
     }
-    // per plane: x (left) then y (right); then z across planes, per row
-    if ((r2 = gemm(hb, dtype_, n0, n1, n0, S_[0], n0, 0, in, p, zp, mid, p, zp, n2)) != SC_OK) return r2;
-    if ((r2 = gemm(hb, dtype_, n0, n1, n1, mid, p, zp, S_[1], n1, 0, out, p, zp, n2)) != SC_OK) return r2;
-    if ((r2 = gemm(hb, dtype_, n0, n2, n2, out, zp, p, S_[2], n2, 0, mid, zp, p, n1)) != SC_OK) return r2;
+    if ((e = transform(r, z, tmp)) != SC_OK) return e;  // S r in tmp (3 passes)
+    SC_HIP_CHECK(launch_pc_scale(dtype_, tmp, lay, n_, lam_[0], lam_[1], lam_[2], s, st));
+    if ((e = transform(tmp, tmp, z)) != SC_OK) return e;  // result in z
+    return SC_OK;
+  }
+  // Sine transforms split by the transform's even/odd symmetry (half the
+  // flops of the full product; see launch_pc_init_split): along an axis of
+  // n points, a butterfly folds the data into sums (first ceil(n/2)) and
+  // reversed differences (last floor(n/2)), and two half-size GEMMs give
+  // the transform with its even rows first and its odd rows after (the
+  // order lam is stored in); the transposed half products followed by the
+  // same butterfly bring such data back to natural order.
+  const size_t es = dtype_ == SC_F64 ? 8 : 4;
+  const int64_t N[3] = {n0, n1, n2};
+  auto hpf = [&](int a) { return (N[a] + 1) / 2; };
+  auto hmf = [&](int a) { return N[a] / 2; };
+  auto Fo = [&](int a) { return static_cast<const void*>(S_[a]); };
+  auto FeR = [&](int a) {
+    return static_cast<const void*>(static_cast<const char*>(S_[a]) + (size_t)(hpf(a) * hpf(a)) * es);
+  };
+  auto off = [&](const void* q, int64_t elems) { return static_cast<const char*>(q) + elems * (int64_t)es; };
+  auto offm = [&](void* q, int64_t elems) { return static_cast<char*>(q) + elems * (int64_t)es; };
+  // along x (left products, per plane): out[0:hp] = Fo U[0:hp],
+  // out[hp:n0] = FeR U[hp:n0]; inverse: the transposes
+  auto along_x = [&](const void* U, void* out, bool inv) -> sc_status {
+    sc_status r2;
+    const int64_t hp = hpf(0), hm = hmf(0), zb = dim_ == 3 ? zp : 0;
+    if ((r2 = gemm(hb, dtype_, hp, n1, hp, Fo(0), hp, 0, U, p, zb, out, p, zb, n2, inv, false)) != SC_OK) return r2;
+    if (hm == 0) return SC_OK;
+    return gemm(hb, dtype_, hm, n1, hm, FeR(0), hm, 0, off(U, hp), p, zb, offm(out, hp), p, zb, n2, inv, false);
+  };
+  // along y (right products, per plane) and along z (right products on
+  // the x-z view of each y row): out[:, 0:hp] = U[:, 0:hp] Fo^T, ...
+  auto along_yz = [&](int a, const void* U, void* out, bool inv) -> sc_status {
+    sc_status r2;
+    const int64_t hp = hpf(a), hm = hmf(a);
+    const int64_t ld = a == 1 ? p : zp, bs = a == 1 ? (dim_ == 3 ? zp : 0) : p, nb = a == 1 ? n2 : n1;
+    if ((r2 = gemm(hb, dtype_, n0, hp, hp, U, ld, bs, Fo(a), hp, 0, out, ld, bs, nb, false, !inv)) != SC_OK)
+      return r2;
+    if (hm == 0) return SC_OK;
+    return gemm(hb, dtype_, n0, hm, hm, off(U, hp * ld), ld, bs, FeR(a), hm, 0, offm(out, hp * ld), ld, bs, nb, false,
+                !inv);
+  };
+  auto fly = [&](const void* in, void* out, int a) -> sc_status {
+    SC_HIP_CHECK(launch_butterfly(dtype_, in, out, lay, n_, a, st));
     return SC_OK;
   };
   if (dim_ == 2) {
-    if ((e = transform(r, z, tmp)) != SC_OK) return e;  // S r in z (via tmp)
-    SC_HIP_CHECK(launch_pc_scale(dtype_, z, lay, n_, lam_[0], lam_[1], nullptr, s, st));
-    return transform(z, z, tmp);  // S (...) back into z
+    if ((e = fly(r, tmp, 0)) != SC_OK || (e = along_x(tmp, z, false)) != SC_OK || (e = fly(z, z, 1)) != SC_OK ||
+        (e = along_yz(1, z, tmp, false)) != SC_OK)
+      return e;
+    SC_HIP_CHECK(launch_pc_scale(dtype_, tmp, lay, n_, lam_[0], lam_[1], nullptr, s, st));
+    if ((e = along_x(tmp, z, true)) != SC_OK || (e = fly(z, z, 0)) != SC_OK ||
+        (e = along_yz(1, z, tmp, true)) != SC_OK)
+      return e;
+    return fly(tmp, z, 1);
   }
-  if ((e = transform(r, z, tmp)) != SC_OK) return e;  // S r in tmp (3 passes)
-  SC_HIP_CHECK(launch_pc_scale(dtype_, tmp, lay, n_, lam_[0], lam_[1], lam_[2], s, st));
-  if ((e = transform(tmp, tmp, z)) != SC_OK) return e;  // result in z
-  return SC_OK;
+  if ((e = fly(r, tmp, 0)) != SC_OK || (e = along_x(tmp, z, false)) != SC_OK || (e = fly(z, z, 1)) != SC_OK ||
+      (e = along_yz(1, z, tmp, false)) != SC_OK || (e = fly(tmp, tmp, 2)) != SC_OK ||
+      (e = along_yz(2, tmp, z, false)) != SC_OK)
+    return e;
+  SC_HIP_CHECK(launch_pc_scale(dtype_, z, lay, n_, lam_[0], lam_[1], lam_[2], s, st));
+  if ((e = along_yz(2, z, tmp, true)) != SC_OK || (e = fly(tmp, tmp, 2)) != SC_OK ||
+      (e = along_yz(1, tmp, z, true)) != SC_OK || (e = fly(z, z, 1)) != SC_OK || (e = along_x(z, tmp, true)) != SC_OK)
+    return e;
+  return fly(tmp, z, 0);
 }
 
 }  // namespace sc

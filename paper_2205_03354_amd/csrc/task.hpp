@@ -78,6 +78,7 @@ class FastPoisson {
   void* tr_ = nullptr;   // the x-transformed field, transposed (n0 rows of n1)
   int dim_ = 2;
   int dtype_ = SC_F64;
+  bool split_ = false;  // GEMM transforms split by the sine matrix's even/odd symmetry
   int64_t n_[3] = {1, 1, 1};
   void* S_[3] = {nullptr, nullptr, nullptr};
   double* lam_[3] = {nullptr, nullptr, nullptr};
@@ -85,6 +86,7 @@ class FastPoisson {
 };
 size_t fastpoisson_bytes(int dim, const int64_t* n, int dtype);
 constexpr int64_t kFftMinSide = 200;  // 2D sides from which the transforms may use FFTs
+constexpr int64_t kSplitMinSide = 768;  // 2D GEMM-transform sides from which the transforms are split
 
 class SolveTask {
  public:
