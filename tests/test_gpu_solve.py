@@ -359,3 +359,20 @@ def test_folded_update_finish_is_bit_identical(native, case):
     assert s1.rel_residual <= 1e-10 and s2.rel_residual <= 1e-10
     assert s1.iterations == s2.iterations, (s1, s2)
     assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("N", [801, 900])
+def test_split_sine_transforms_match_full_products(native, monkeypatch, N):
+    # 2D sides >= 768 split each GEMM sine transform by the matrix's even /
+    # odd symmetry (odd and even interior sizes here); the preconditioned
+    # solve converges either way, the oracle confirms both residuals, and
+    # the two solutions agree to kappa times the tolerance
+    sols = []
+    for mode in ("1", "0"):
+        monkeypatch.setenv("SCOMP_PCSPLIT", mode)
+        bvp, x, st = _gpu_bvp(native, 2, N, native.SC_PREC_F64, precond=native.SC_PC_FASTPOISSON)
+        assert st.status == native.SC_OK and st.rel_residual <= 1e-10, (mode, st)
+        rel = OP.bvp_relres_extended(R.biharmonic(2), x, bvp.f, bvp.g, bvp.halo, bvp.h)
+        assert rel <= 1e-10, (mode, rel)
+        sols.append(x)
+    assert np.max(np.abs(sols[0] - sols[1])) <= 1e-7 * np.max(np.abs(sols[1]))
